@@ -1,0 +1,195 @@
+/*
+ * frntt -- number-theoretic transforms over the BN254 scalar field Fr on
+ * AMD MI355X (gfx950). C ABI of libfrntt.so.
+ *
+ * The operation (paper: Background, "Number Theory Transformation"): for a
+ * vector x of N = 2^log_n field elements,
+ *     X_k = sum_{n<N} x_n * w^(k*n)  mod r,     k in [0, N),
+ * with r the 254-bit BN254 scalar-field prime and w = 5^((r-1)/N) a
+ * primitive N-th root of unity (5 generates Fr^*). The inverse transform
+ * uses w^-1 and scales by N^-1; the coset transform evaluates at g*w^k with
+ * g = 5, i.e. it transforms x_n * g^n; the coset inverse undoes it.
+ * Batching follows the paper's batch-size study (Ablation Study - Batch
+ * Size): `batch` independent polynomials in one call.
+ *
+ * Data layout (all entry points): an element is 32 bytes, four 64-bit
+ * little-endian limbs of a canonical integer in [0, r). A polynomial is
+ * 2^log_n consecutive elements in natural order; `batch` polynomials are
+ * consecutive. Transforms are in place, input and output in natural order.
+ *
+ * Memory ownership: the caller allocates and owns every data buffer (device
+ * memory, e.g. hipMalloc or a torch tensor) and keeps it alive until the
+ * stream has passed the call. The context owns its twiddle and limb tables
+ * and its scratch space.
+ *
+ * Asynchrony: every transform call is enqueued on `stream` (a hipStream_t;
+ * NULL means the null stream) and returns at once. Argument errors are
+ * returned synchronously before anything is enqueued. A failed HIP launch
+ * returns FRNTT_EHIP and frntt_last_hip_error() gives the hipError_t.
+ *
+ * Preconditions: inputs must be canonical (< r). With the FRNTT_VALIDATE
+ * context flag a device check runs before each transform; a violation is
+ * reported by frntt_check_inputs(). Otherwise the output for inputs >= r is
+ * unspecified (but the call never reads or writes out of bounds).
+ *
+ * Threads and streams: a context may be used from several host threads and
+ * streams at once. Calls on different streams get separate scratch space.
+ */
+#ifndef FRNTT_H
+#define FRNTT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct frntt_ctx frntt_ctx;
+typedef struct frntt_server frntt_server;
+
+/* Status codes returned by every call. */
+enum {
+    FRNTT_OK = 0,
+    FRNTT_EINVAL = -1, /* null pointer, bad kind/algorithm/flag, batch < 0     */
+    FRNTT_ERANGE = -2, /* log_n outside [0, max_log_n] or above 28            */
+    FRNTT_EALIGN = -3, /* data pointer not 32-byte aligned                    */
+    FRNTT_ENOMEM = -4, /* device or host allocation failed                    */
+    FRNTT_EHIP = -5,   /* a HIP runtime call failed (see frntt_last_hip_error) */
+    FRNTT_EBUSY = -6,  /* server: over its memory budget or queue limit       */
+    FRNTT_ESTATE = -7  /* object in the wrong state (e.g. unknown ticket)     */
+};
+
+/* Transform kinds. */
+enum { FRNTT_FWD = 0, FRNTT_INV = 1, FRNTT_COSET = 2, FRNTT_COSET_INV = 3 };
+
+/* Algorithms.
+ * BUTTERFLY: radix-2/4 Cooley-Tukey stages with Montgomery twiddle products
+ *   on the vector ALUs (the paper's butterfly NTT; Dataflow Optimizations).
+ * FOURSTEP_MFMA: the matrix form (the paper's 3-step NTT and its recursive
+ *   5-step refinement, Eq. 1): sub-DFTs as byte-limb x twiddle products on
+ *   int8 matrix cores with 32-bit accumulators, then carry merge and
+ *   reduction mod r (Alg. 1's ByteDecompose / einsum / ByteMerge pattern).
+ * AUTO: the context's tuned choice per size (MFMA unless tuned otherwise). */
+enum { FRNTT_ALGO_AUTO = 0, FRNTT_ALGO_BUTTERFLY = 1, FRNTT_ALGO_FOURSTEP_MFMA = 2 };
+
+/* Context flags. */
+enum {
+    FRNTT_VALIDATE = 1u << 0  /* check inputs < r on the device before transforming */
+};
+
+/* Create a context on HIP device `hip_device` for sizes up to 2^max_log_n
+ * (1 <= max_log_n <= 28). Builds all twiddle and limb tables on the device.
+ * *out is set only on success. Errors: EINVAL, ERANGE, ENOMEM, EHIP. */
+int frntt_ctx_create(frntt_ctx **out, int hip_device, int max_log_n, unsigned flags);
+
+/* Destroy a context (waits for the device). NULL is accepted. */
+int frntt_ctx_destroy(frntt_ctx *ctx);
+
+/* In-place transforms of `batch` consecutive polynomials of 2^log_n
+ * elements at device pointer `data`. batch == 0 is a no-op; log_n == 0 is
+ * the identity. Errors: EINVAL (ctx or data NULL, batch < 0), ERANGE,
+ * EALIGN, ENOMEM (scratch), EHIP. */
+int ntt_fwd(frntt_ctx *ctx, void *data, int log_n, int batch, void *stream);
+int ntt_inv(frntt_ctx *ctx, void *data, int log_n, int batch, void *stream);
+int ntt_coset(frntt_ctx *ctx, void *data, int log_n, int batch, void *stream);     /* g = 5 */
+int ntt_coset_inv(frntt_ctx *ctx, void *data, int log_n, int batch, void *stream);
+/* Same, with the kind as an argument (FRNTT_FWD .. FRNTT_COSET_INV). */
+int ntt_transform(frntt_ctx *ctx, void *data, int log_n, int batch, int kind, void *stream);
+
+/* As ntt_transform, with an explicit algorithm that overrides the context's
+ * choice for this call only. */
+int ntt_transform_algo(frntt_ctx *ctx, void *data, int log_n, int batch, int kind, int algo,
+                       void *stream);
+
+/* Choose the algorithm used by later calls (FRNTT_ALGO_*). */
+int frntt_set_algo(frntt_ctx *ctx, int algo);
+int frntt_get_algo(const frntt_ctx *ctx);
+
+/* Override the decomposition of 2^log_n into HBM passes for one algorithm:
+ * pass_logs[0..n_passes-1] are the log2 radices of the passes, in order,
+ * each in [1, 12], summing to log_n. n_passes == 0 restores the default.
+ * Any valid plan gives bit-identical results. Errors: EINVAL, ERANGE. */
+int frntt_set_plan(frntt_ctx *ctx, int algo, int log_n, const int *pass_logs, int n_passes);
+/* The plan in use; writes up to `cap` entries, returns the pass count (>= 0)
+ * or an error. */
+int frntt_get_plan(const frntt_ctx *ctx, int algo, int log_n, int *pass_logs, int cap);
+
+/* One job of an uneven batch: a polynomial of 2^log_n elements at `data`. */
+typedef struct {
+    void *data;
+    int log_n;
+    int kind;
+} frntt_job;
+
+/* Uneven batch (paper: Ablation Study - Batch Size): transform every job in
+ * place with ONE persistent kernel launch. The descriptors are copied before
+ * the call returns; the data buffers must stay alive until the stream passes
+ * the call. Jobs must not overlap in memory. Errors as for ntt_transform,
+ * per job, plus EINVAL for n_jobs < 0 or jobs == NULL with n_jobs > 0. */
+int ntt_batch(frntt_ctx *ctx, const frntt_job *jobs, int n_jobs, void *stream);
+
+/* Graph form of ntt_batch for repeated identical batches: the first call for
+ * a given job list captures the launch into a hipGraph; later calls with the
+ * same list replay it. Results are identical to ntt_batch. */
+int ntt_batch_graph(frntt_ctx *ctx, const frntt_job *jobs, int n_jobs, void *stream);
+
+/* Autotuner: time the candidate plans (algorithm, pass split, launch shape)
+ * for one size and batch on `stream`, keep the fastest in the context, and
+ * return it through the out-parameters (any may be NULL). */
+int frntt_tune(frntt_ctx *ctx, int log_n, int batch, int *best_algo, int *best_passes,
+               float *best_ms, void *stream);
+/* Save / load the tuned choices as a small JSON file. */
+int frntt_tune_save(const frntt_ctx *ctx, const char *path);
+int frntt_tune_load(frntt_ctx *ctx, const char *path);
+
+/* Fill `count` elements at `data` on the device with the seeded uniform
+ * elements of [0, r) that the project's input generator defines (SplitMix64
+ * counter stream `stream_id`, starting at element `start`). */
+int frntt_generate(frntt_ctx *ctx, void *data, uint64_t seed, uint64_t stream_id, uint64_t start,
+                   uint64_t count, void *stream);
+
+/* With FRNTT_VALIDATE: waits for the device and returns EINVAL if any input
+ * seen since the last check was >= r, else OK. Without the flag: OK. */
+int frntt_check_inputs(frntt_ctx *ctx);
+
+/* Scratch bytes a transform of this size needs (informational). */
+size_t frntt_scratch_bytes(int log_n, int batch);
+
+/* Last hipError_t seen by the context (0 if none). */
+int frntt_last_hip_error(const frntt_ctx *ctx);
+/* Static description of a status code. */
+const char *frntt_strerror(int status);
+
+/* ---- serving: continuous batching of requests (see frntt_server_*) ----
+ * A server owns a worker thread, `slots` streams and a device memory pool
+ * bounded by `hbm_budget_bytes` (twiddle tables included). Requests are
+ * admitted in arrival order while their buffers fit the budget; admitted
+ * requests are grouped into batches and launched on a free slot stream, so
+ * work that arrives while other batches run overlaps with them.
+ * Request data are generated on the device from (data_seed, request id),
+ * using the same generator as frntt_generate with stream_id = request id.
+ */
+int frntt_server_create(frntt_server **out, frntt_ctx *ctx, size_t hbm_budget_bytes, int slots);
+/* Queue a request; returns its ticket. EBUSY if the request alone exceeds
+ * the budget. */
+int frntt_server_submit(frntt_server *srv, int kind, int log_n, uint64_t data_seed,
+                        uint64_t *ticket);
+/* done = 1 once the result is on the device; latency_ms = completion time
+ * minus submit time (host clock). ESTATE for an unknown ticket. */
+int frntt_server_poll(frntt_server *srv, uint64_t ticket, int *done, double *latency_ms);
+/* Copy a finished request's result (2^log_n elements) to host memory and
+ * release its buffer. ESTATE if not finished or unknown. */
+int frntt_server_result(frntt_server *srv, uint64_t ticket, void *host_out);
+/* Release a finished request's buffer without copying. */
+int frntt_server_release(frntt_server *srv, uint64_t ticket);
+/* Counters: requests completed, batches launched, peak bytes in flight. */
+int frntt_server_stats(frntt_server *srv, uint64_t *completed, uint64_t *batches,
+                       uint64_t *peak_bytes);
+/* Wait for all submitted requests, stop the worker, free everything. */
+int frntt_server_destroy(frntt_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FRNTT_H */

@@ -1,0 +1,11 @@
+"""frntt: BN254-Fr number-theoretic transforms on AMD MI355X (gfx950).
+
+The transforms run in libfrntt.so (hand-written HIP kernels behind a C ABI,
+declared in include/frntt.h). This package only marshals arguments to it;
+see ``paper_2604_17808_amd.frntt``.
+"""
+from .frntt import (FWD, INV, COSET, COSET_INV, ALGO_AUTO, ALGO_BUTTERFLY, ALGO_FOURSTEP_MFMA,
+                    FrnttError, Context, Server, lib, library_path)
+
+__all__ = ["FWD", "INV", "COSET", "COSET_INV", "ALGO_AUTO", "ALGO_BUTTERFLY",
+           "ALGO_FOURSTEP_MFMA", "FrnttError", "Context", "Server", "lib", "library_path"]

@@ -1,0 +1,452 @@
+// Host side of libfrntt: contexts, plans, scratch, launches and the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "frntt_internal.hpp"
+
+namespace frntt {
+
+int build_tables(frntt_ctx* ctx);
+
+int set_hip_error(const frntt_ctx* ctx, hipError_t e) {
+  if (ctx) ctx->last_hip_error = (int)e;
+  return e == hipSuccess ? FRNTT_OK : FRNTT_EHIP;
+}
+
+// RAII guard that makes `dev` current and restores the caller's device.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) hipSetDevice(prev);
+  }
+};
+
+// ------------------------------------------------------------------ plans
+
+// Split a pass radix 2^l into levels of at most 2^max_m, as even as possible.
+static int split_levels(int l, int max_m, int* out) {
+  int n = (l + max_m - 1) / max_m;
+  if (n < 1) n = 1;
+  int base = l / n, extra = l % n;
+  for (int i = 0; i < n; ++i) out[i] = base + (i < extra ? 1 : 0);
+  return n;
+}
+
+// Can level m of a pass with 2^log_t staged elements run on MFMA? Every wave
+// takes the same number of 32-vector tiles, and tiles x radix <= 16 keeps a
+// wave's data fragments in 64 registers.
+bool mfma_level_ok(int m, int log_t) {
+  if (m < 1 || m > 4) return false;
+  const int tiles_log = log_t - m - 5;
+  if (tiles_log < 3) return false;  // 8 waves
+  const int tpw_log = tiles_log - 3;
+  return tpw_log + m <= 4;
+}
+
+// Levels of pass p for the MFMA engine: radices of at most 16, as even as
+// possible. Returns false if some level cannot run on MFMA with 2^log_t
+// staged elements (the pass then runs on the butterfly engine).
+static bool plan_levels(Plan& plan, int p, int log_t_pass) {
+  const int l = plan.pass_log[p];
+  int levs[kMaxLevels];
+  const int n = split_levels(l, 4, levs);
+  plan.nlev[p] = n;
+  bool ok = n <= kMaxLevels;
+  for (int i = 0; i < n; ++i) {
+    plan.lev_log[p][i] = levs[i];
+    ok = ok && mfma_level_ok(levs[i], log_t_pass);
+  }
+  return ok;
+}
+
+static void default_pass_split(int log_n, int* n_pass, int* pl) {
+  if (log_n <= 12) {
+    *n_pass = 1;
+    pl[0] = log_n;
+  } else if (log_n <= 24) {
+    *n_pass = 2;
+    pl[0] = (log_n + 1) / 2;
+    pl[1] = log_n / 2;
+  } else {
+    *n_pass = 3;
+    pl[0] = (log_n + 2) / 3;
+    pl[1] = (log_n + 1) / 3;
+    pl[2] = log_n / 3;
+  }
+}
+
+int check_plan_valid(const Plan& p, int log_n) {
+  if (p.n_pass < 1 || p.n_pass > 4) return FRNTT_EINVAL;
+  int s = 0;
+  for (int i = 0; i < p.n_pass; ++i) {
+    if (p.pass_log[i] < 1 || p.pass_log[i] > kMaxLogT) return FRNTT_EINVAL;
+    s += p.pass_log[i];
+  }
+  return s == log_n ? FRNTT_OK : FRNTT_EINVAL;
+}
+
+Plan plan_for(const frntt_ctx* ctx, int algo, int log_n) {
+  Plan plan;
+  if (ctx && ctx->has_override[algo][log_n]) {
+    plan = ctx->plan_override[algo][log_n];
+  } else if (ctx && ctx->has_tuned[log_n] && ctx->tuned[log_n].algo == algo) {
+    plan.n_pass = ctx->tuned[log_n].n_pass;
+    for (int i = 0; i < 4; ++i) plan.pass_log[i] = ctx->tuned[log_n].pass_log[i];
+  } else {
+    default_pass_split(log_n, &plan.n_pass, plan.pass_log);
+  }
+  return plan;
+}
+
+int effective_algo(const frntt_ctx* ctx, int log_n, int requested) {
+  int a = requested;
+  if (a == FRNTT_ALGO_AUTO) a = ctx->algo;
+  if (a == FRNTT_ALGO_AUTO) {
+    if (ctx->has_tuned[log_n]) a = ctx->tuned[log_n].algo;
+    else a = FRNTT_ALGO_FOURSTEP_MFMA;
+  }
+  return a;
+}
+
+size_t scratch_bytes_for(int log_n, int batch, int n_pass) {
+  if (n_pass <= 1) return 0;
+  return ((size_t)batch << log_n) * 32;
+}
+
+// Lines per workgroup for pass p: fill 2^12 staged elements, but never span
+// more lines than one contiguous group holds, and divide the line count.
+static int pass_log_g(const Plan& plan, int p, int log_n, int batch) {
+  const int l = plan.pass_log[p];
+  int lg = kMaxLogT - l;
+  const bool last = (p == plan.n_pass - 1);
+  int s = 0;
+  for (int q = p + 1; q < plan.n_pass; ++q) s += plan.pass_log[q];
+  int d = log_n - l - s;
+  if (!last) {
+    lg = std::min(lg, s);
+  } else if (plan.n_pass > 1) {
+    lg = std::min(lg, d);
+  } else {
+    // single pass: lines are whole polynomials; G must divide the batch
+    int b = batch, tz = 0;
+    while (b > 0 && (b & 1) == 0 && tz < 30) {
+      b >>= 1;
+      ++tz;
+    }
+    lg = std::min(lg, tz);
+  }
+  return std::max(lg, 0);
+}
+
+int build_passes(const frntt_ctx* ctx, const Plan& plan_in, int log_n, int batch, int kind, void* data,
+                 void* scratch, std::vector<PassParams>* out, int algo) {
+  Plan plan = plan_in;
+  out->clear();
+  const int dir = (kind == FRNTT_INV || kind == FRNTT_COSET_INV) ? 1 : 0;
+  int d = 0;
+  for (int p = 0; p < plan.n_pass; ++p) {
+    const int l = plan.pass_log[p];
+    int s = 0;
+    for (int q = p + 1; q < plan.n_pass; ++q) s += plan.pass_log[q];
+    const int lg = pass_log_g(plan, p, log_n, batch);
+    const int log_t = l + lg;
+    const bool mfma_ok = plan_levels(plan, p, log_t);
+    PassParams P{};
+    const bool first = p == 0, last = p == plan.n_pass - 1;
+    P.src = (const u32x4*)(first ? data : scratch);
+    P.dst = (u32x4*)(last ? data : scratch);
+    P.log_n = log_n;
+    P.log_r = l;
+    P.log_s = s;
+    P.log_d = d;
+    P.log_g = lg;
+    P.log_t = log_t;
+    P.is_last = last ? 1 : 0;
+    P.n_pass = plan.n_pass;
+    for (int i = 0; i < 4; ++i) P.pass_log[i] = plan.pass_log[i];
+    P.nlev = plan.nlev[p];
+    for (int i = 0; i < kMaxLevels; ++i) P.lev_log[i] = plan.lev_log[p][i];
+    P.engine = (algo == FRNTT_ALGO_FOURSTEP_MFMA && mfma_ok) ? 1 : 0;
+    P.dir = dir;
+    P.coset_pre = (first && kind == FRNTT_COSET) ? 1 : 0;
+    P.post = 0;
+    if (last && kind == FRNTT_INV) P.post = 1;
+    if (last && kind == FRNTT_COSET_INV) P.post = 2;
+    const int64_t lines = ((int64_t)batch << log_n) >> l;
+    P.wg_count = lines >> lg;
+    P.xcd_remap = 1;
+    out->push_back(P);
+    d += l;
+  }
+  return FRNTT_OK;
+}
+
+int get_scratch(frntt_ctx* ctx, hipStream_t stream, size_t bytes, void** out) {
+  *out = nullptr;
+  if (bytes == 0) return FRNTT_OK;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  Scratch& s = ctx->scratch[stream];
+  if (s.bytes < bytes) {
+    if (s.ptr) {
+      // the old buffer may still be in use by work queued on this stream
+      hipError_t e = hipStreamSynchronize(stream);
+      if (e != hipSuccess) return set_hip_error(ctx, e);
+      hipFree(s.ptr);
+      s.ptr = nullptr;
+      s.bytes = 0;
+    }
+    hipError_t e = hipMalloc(&s.ptr, bytes);
+    if (e != hipSuccess) {
+      s.ptr = nullptr;
+      set_hip_error(ctx, e);
+      return FRNTT_ENOMEM;
+    }
+    s.bytes = bytes;
+  }
+  *out = s.ptr;
+  return FRNTT_OK;
+}
+
+int launch_passes(frntt_ctx* ctx, const std::vector<PassParams>& passes, int algo, hipStream_t stream) {
+  for (const PassParams& P : passes) {
+    if (P.wg_count <= 0) continue;
+    (void)algo;
+    if (P.engine == 1)
+      hipLaunchKernelGGL(ntt_pass_mfma_kernel, dim3((unsigned)P.wg_count), dim3(kThreads), 0, stream, P,
+                         ctx->tables);
+    else
+      hipLaunchKernelGGL(ntt_pass_bfly_kernel, dim3((unsigned)P.wg_count), dim3(kThreads), 0, stream, P,
+                         ctx->tables);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_hip_error(ctx, e);
+  }
+  return FRNTT_OK;
+}
+
+static int validate_inputs(frntt_ctx* ctx, void* data, int log_n, int batch, hipStream_t stream) {
+  const uint64_t count = (uint64_t)batch << log_n;
+  const unsigned blocks = (unsigned)((count + 255) / 256);
+  hipLaunchKernelGGL(validate_kernel, dim3(blocks), dim3(256), 0, stream, (const u32x4*)data, count,
+                     ctx->valid_flag);
+  return set_hip_error(ctx, hipGetLastError());
+}
+
+int transform_impl(frntt_ctx* ctx, void* data, int log_n, int batch, int kind, int algo_req,
+                   hipStream_t stream, void* workspace, size_t ws_bytes) {
+  if (!ctx || (!data && batch > 0)) return FRNTT_EINVAL;
+  if (batch < 0 || kind < FRNTT_FWD || kind > FRNTT_COSET_INV) return FRNTT_EINVAL;
+  if (algo_req < FRNTT_ALGO_AUTO || algo_req > FRNTT_ALGO_FOURSTEP_MFMA) return FRNTT_EINVAL;
+  if (log_n < 0 || log_n > ctx->max_log_n || log_n > kMasterLog) return FRNTT_ERANGE;
+  if (((uintptr_t)data & 31) != 0) return FRNTT_EALIGN;
+  if (batch == 0) return FRNTT_OK;
+  if ((((int64_t)batch) << log_n) > ((int64_t)1 << 40)) return FRNTT_ERANGE;
+  DeviceGuard guard(ctx->device);
+  if (ctx->flags & FRNTT_VALIDATE) {
+    int rc = validate_inputs(ctx, data, log_n, batch, stream);
+    if (rc) return rc;
+  }
+  if (log_n == 0) return FRNTT_OK;  // identity (N^-1 = 1, g^0 = 1)
+  const int algo = effective_algo(ctx, log_n, algo_req);
+  Plan plan = plan_for(ctx, algo, log_n);
+  const size_t need = scratch_bytes_for(log_n, batch, plan.n_pass);
+  void* scratch = nullptr;
+  if (need) {
+    if (workspace) {
+      if (ws_bytes < need) return FRNTT_EINVAL;
+      scratch = workspace;
+    } else {
+      int rc = get_scratch(ctx, stream, need, &scratch);
+      if (rc) return rc;
+    }
+  }
+  std::vector<PassParams> passes;
+  int rc = build_passes(ctx, plan, log_n, batch, kind, data, scratch, &passes, algo);
+  if (rc) return rc;
+  return launch_passes(ctx, passes, algo, stream);
+}
+
+}  // namespace frntt
+
+using namespace frntt;
+
+// ---------------------------------------------------------------- C ABI
+
+extern "C" {
+
+int frntt_ctx_create(frntt_ctx** out, int hip_device, int max_log_n, unsigned flags) {
+  if (!out) return FRNTT_EINVAL;
+  *out = nullptr;
+  if (max_log_n < 1 || max_log_n > kMasterLog) return FRNTT_ERANGE;
+  if (flags & ~(unsigned)FRNTT_VALIDATE) return FRNTT_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev)
+    return FRNTT_EINVAL;
+  frntt_ctx* ctx = new (std::nothrow) frntt_ctx();
+  if (!ctx) return FRNTT_ENOMEM;
+  ctx->device = hip_device;
+  ctx->max_log_n = max_log_n;
+  ctx->flags = flags;
+  DeviceGuard guard(hip_device);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess) ctx->cu_count = prop.multiProcessorCount;
+  if (ctx->cu_count <= 0) ctx->cu_count = 256;
+  int rc = build_tables(ctx);
+  if (rc == FRNTT_OK) {
+    hipError_t e = hipMalloc((void**)&ctx->valid_flag, 256);
+    if (e != hipSuccess) rc = FRNTT_ENOMEM;
+    else if (hipMemset(ctx->valid_flag, 0, 256) != hipSuccess) rc = FRNTT_EHIP;
+  }
+  if (rc == FRNTT_OK && hipEventCreateWithFlags(&ctx->batch_host_event, hipEventDisableTiming) != hipSuccess)
+    rc = FRNTT_EHIP;
+  if (rc != FRNTT_OK) {
+    frntt_ctx_destroy(ctx);
+    return rc;
+  }
+  *out = ctx;
+  return FRNTT_OK;
+}
+
+int frntt_ctx_destroy(frntt_ctx* ctx) {
+  if (!ctx) return FRNTT_OK;
+  {
+    DeviceGuard guard(ctx->device);
+    hipDeviceSynchronize();
+    for (auto& kv : ctx->scratch)
+      if (kv.second.ptr) hipFree(kv.second.ptr);
+    for (auto& g : ctx->graphs) {
+      if (g.exec) hipGraphExecDestroy(g.exec);
+      if (g.graph) hipGraphDestroy(g.graph);
+      if (g.dev_buf) hipFree(g.dev_buf);
+    }
+    if (ctx->batch_buf) hipFree(ctx->batch_buf);
+    if (ctx->batch_host) hipHostFree(ctx->batch_host);
+    if (ctx->batch_host_event) hipEventDestroy(ctx->batch_host_event);
+    if (ctx->valid_flag) hipFree(ctx->valid_flag);
+    if (ctx->table_mem) hipFree(ctx->table_mem);
+  }
+  delete ctx;
+  return FRNTT_OK;
+}
+
+int ntt_transform(frntt_ctx* ctx, void* data, int log_n, int batch, int kind, void* stream) {
+  return transform_impl(ctx, data, log_n, batch, kind, FRNTT_ALGO_AUTO, (hipStream_t)stream, nullptr, 0);
+}
+
+int ntt_transform_algo(frntt_ctx* ctx, void* data, int log_n, int batch, int kind, int algo,
+                       void* stream) {
+  return transform_impl(ctx, data, log_n, batch, kind, algo, (hipStream_t)stream, nullptr, 0);
+}
+
+int ntt_fwd(frntt_ctx* ctx, void* data, int log_n, int batch, void* stream) {
+  return ntt_transform(ctx, data, log_n, batch, FRNTT_FWD, stream);
+}
+int ntt_inv(frntt_ctx* ctx, void* data, int log_n, int batch, void* stream) {
+  return ntt_transform(ctx, data, log_n, batch, FRNTT_INV, stream);
+}
+int ntt_coset(frntt_ctx* ctx, void* data, int log_n, int batch, void* stream) {
+  return ntt_transform(ctx, data, log_n, batch, FRNTT_COSET, stream);
+}
+int ntt_coset_inv(frntt_ctx* ctx, void* data, int log_n, int batch, void* stream) {
+  return ntt_transform(ctx, data, log_n, batch, FRNTT_COSET_INV, stream);
+}
+
+int frntt_set_algo(frntt_ctx* ctx, int algo) {
+  if (!ctx || algo < FRNTT_ALGO_AUTO || algo > FRNTT_ALGO_FOURSTEP_MFMA) return FRNTT_EINVAL;
+  ctx->algo = algo;
+  return FRNTT_OK;
+}
+
+int frntt_get_algo(const frntt_ctx* ctx) { return ctx ? ctx->algo : FRNTT_EINVAL; }
+
+int frntt_set_plan(frntt_ctx* ctx, int algo, int log_n, const int* pass_logs, int n_passes) {
+  if (!ctx || algo < FRNTT_ALGO_BUTTERFLY || algo > FRNTT_ALGO_FOURSTEP_MFMA) return FRNTT_EINVAL;
+  if (log_n < 1 || log_n > kMasterLog) return FRNTT_ERANGE;
+  if (n_passes == 0) {
+    ctx->has_override[algo][log_n] = false;
+    return FRNTT_OK;
+  }
+  if (!pass_logs || n_passes < 0 || n_passes > 4) return FRNTT_EINVAL;
+  Plan p;
+  p.n_pass = n_passes;
+  for (int i = 0; i < n_passes; ++i) p.pass_log[i] = pass_logs[i];
+  int rc = check_plan_valid(p, log_n);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->plan_override[algo][log_n] = p;
+  ctx->has_override[algo][log_n] = true;
+  return FRNTT_OK;
+}
+
+int frntt_get_plan(const frntt_ctx* ctx, int algo, int log_n, int* pass_logs, int cap) {
+  if (!ctx || algo < FRNTT_ALGO_AUTO || algo > FRNTT_ALGO_FOURSTEP_MFMA) return FRNTT_EINVAL;
+  if (log_n < 1 || log_n > kMasterLog) return FRNTT_ERANGE;
+  const int a = effective_algo(ctx, log_n, algo);
+  Plan p = plan_for(ctx, a, log_n);
+  for (int i = 0; i < p.n_pass && i < cap; ++i)
+    if (pass_logs) pass_logs[i] = p.pass_log[i];
+  return p.n_pass;
+}
+
+size_t frntt_scratch_bytes(int log_n, int batch) {
+  if (log_n < 0 || log_n > kMasterLog || batch < 0) return 0;
+  int n_pass, pl[4];
+  default_pass_split(log_n, &n_pass, pl);
+  return scratch_bytes_for(log_n, batch, n_pass);
+}
+
+int frntt_generate(frntt_ctx* ctx, void* data, uint64_t seed, uint64_t stream_id, uint64_t start,
+                   uint64_t count, void* stream) {
+  if (!ctx || (!data && count)) return FRNTT_EINVAL;
+  if (((uintptr_t)data & 31) != 0) return FRNTT_EALIGN;
+  if (count == 0) return FRNTT_OK;
+  if (start + count > (1ull << 32)) return FRNTT_ERANGE;
+  DeviceGuard guard(ctx->device);
+  const unsigned blocks = (unsigned)((count + 255) / 256);
+  hipLaunchKernelGGL(generate_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, (u32x4*)data, seed,
+                     stream_id, start, count);
+  return set_hip_error(ctx, hipGetLastError());
+}
+
+int frntt_check_inputs(frntt_ctx* ctx) {
+  if (!ctx) return FRNTT_EINVAL;
+  if (!(ctx->flags & FRNTT_VALIDATE)) return FRNTT_OK;
+  DeviceGuard guard(ctx->device);
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return set_hip_error(ctx, e);
+  unsigned int flag = 0;
+  e = hipMemcpy(&flag, ctx->valid_flag, sizeof flag, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return set_hip_error(ctx, e);
+  if (flag) {
+    e = hipMemset(ctx->valid_flag, 0, sizeof flag);
+    if (e != hipSuccess) return set_hip_error(ctx, e);
+    return FRNTT_EINVAL;
+  }
+  return FRNTT_OK;
+}
+
+int frntt_last_hip_error(const frntt_ctx* ctx) { return ctx ? ctx->last_hip_error : 0; }
+
+const char* frntt_strerror(int status) {
+  switch (status) {
+    case FRNTT_OK: return "ok";
+    case FRNTT_EINVAL: return "invalid argument";
+    case FRNTT_ERANGE: return "size out of range";
+    case FRNTT_EALIGN: return "data pointer not 32-byte aligned";
+    case FRNTT_ENOMEM: return "out of memory";
+    case FRNTT_EHIP: return "HIP runtime error";
+    case FRNTT_EBUSY: return "busy: over budget or queue limit";
+    case FRNTT_ESTATE: return "invalid state";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

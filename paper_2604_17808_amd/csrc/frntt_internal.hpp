@@ -1,0 +1,97 @@
+// Host-side internals of libfrntt: context, plans and launch helpers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/frntt.h"
+#include "ntt_device.hpp"
+
+namespace frntt {
+
+__global__ void ntt_pass_bfly_kernel(PassParams P, DevTables T);
+__global__ void ntt_pass_mfma_kernel(PassParams P, DevTables T);
+__global__ void ntt_batch_kernel(BatchParams B, DevTables T);
+__global__ void generate_kernel(u32x4* out, uint64_t seed, uint64_t stream_id, uint64_t start,
+                                uint64_t count);
+__global__ void validate_kernel(const u32x4* data, uint64_t count, unsigned int* flag);
+__global__ void zero_words_kernel(unsigned int* p, int64_t n);
+
+// Decomposition of one transform size into passes and levels.
+struct Plan {
+  int n_pass = 0;
+  int pass_log[4] = {0, 0, 0, 0};
+  int nlev[4] = {0, 0, 0, 0};
+  int lev_log[4][kMaxLevels] = {};
+  int log_t = 12;   // elements per workgroup (upper bound)
+};
+
+struct Scratch {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+struct GraphEntry {
+  std::vector<frntt_job> jobs;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  void* dev_buf = nullptr;  // descriptors + counters used by the captured launch
+  hipStream_t stream = nullptr;
+};
+
+struct TuneEntry {
+  int algo = FRNTT_ALGO_FOURSTEP_MFMA;
+  int n_pass = 0;
+  int pass_log[4] = {0, 0, 0, 0};
+  float ms = 0.f;
+};
+
+}  // namespace frntt
+
+struct frntt_ctx {
+  int device = 0;
+  int max_log_n = 0;
+  unsigned flags = 0;
+  int algo = FRNTT_ALGO_AUTO;
+  int cu_count = 0;
+  mutable int last_hip_error = 0;
+  void* table_mem = nullptr;       // single device allocation holding all tables
+  size_t table_bytes = 0;
+  frntt::DevTables tables{};
+  unsigned int* valid_flag = nullptr;  // device flag for FRNTT_VALIDATE
+  // plan overrides [algo][log_n]
+  frntt::Plan plan_override[3][29];
+  bool has_override[3][29] = {};
+  frntt::TuneEntry tuned[29];
+  bool has_tuned[29] = {};
+  std::mutex mu;                   // guards scratch, graphs, tuning state
+  std::map<hipStream_t, frntt::Scratch> scratch;
+  std::vector<frntt::GraphEntry> graphs;
+  void* batch_buf = nullptr;       // device descriptors for ntt_batch
+  size_t batch_buf_bytes = 0;
+  void* batch_host = nullptr;      // pinned staging for descriptors
+  size_t batch_host_bytes = 0;
+  hipEvent_t batch_host_event = nullptr;  // marks when batch_host may be reused
+};
+
+namespace frntt {
+
+int set_hip_error(const frntt_ctx* ctx, hipError_t e);
+// Default or overridden plan for (algo, log_n); algo must be BUTTERFLY or MFMA.
+Plan plan_for(const frntt_ctx* ctx, int algo, int log_n);
+// Build the per-pass launch parameters of one transform.
+int build_passes(const frntt_ctx* ctx, const Plan& plan, int log_n, int batch, int kind,
+                 void* data, void* scratch, std::vector<PassParams>* out, int algo);
+int effective_algo(const frntt_ctx* ctx, int log_n, int requested);
+size_t scratch_bytes_for(int log_n, int batch, int n_pass);
+int get_scratch(frntt_ctx* ctx, hipStream_t stream, size_t bytes, void** out);
+int launch_passes(frntt_ctx* ctx, const std::vector<PassParams>& passes, int algo, hipStream_t stream);
+bool mfma_level_ok(int m, int log_t);
+int transform_impl(frntt_ctx* ctx, void* data, int log_n, int batch, int kind, int algo,
+                   hipStream_t stream, void* workspace, size_t ws_bytes);
+int check_plan_valid(const Plan& p, int log_n);
+
+}  // namespace frntt

@@ -1,0 +1,70 @@
+// Small utility kernels: seeded inputs, input validation, zero fill.
+#include "ntt_device.hpp"
+
+namespace frntt {
+
+__device__ FRNTT_INLINE uint64_t mix64(uint64_t z) {
+  z ^= z >> 30;
+  z *= 0xBF58476D1CE4E5B9ull;
+  z ^= z >> 27;
+  z *= 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return z;
+}
+
+// Seeded uniform elements of [0, r) (SplitMix64 counter stream, rejection
+// against r, 64 attempts; see the project's input generator).
+__global__ void generate_kernel(u32x4* out, uint64_t seed, uint64_t stream_id, uint64_t start,
+                                uint64_t count) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const uint64_t base = seed * 0x9E3779B97F4A7C15ull + (stream_id << 40) + ((start + i) << 8);
+  const uint64_t r64[4] = {((uint64_t)FR_R1 << 32) | FR_R0, ((uint64_t)FR_R3 << 32) | FR_R2,
+                           ((uint64_t)FR_R5 << 32) | FR_R4, ((uint64_t)FR_R7 << 32) | FR_R6};
+  uint64_t w[4];
+  for (int t = 0; t < 64; ++t) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) w[j] = mix64(base + ((uint64_t)t << 2) + (uint64_t)j);
+    w[3] &= (1ull << 62) - 1;
+    bool lt = false, eq = true;
+#pragma unroll
+    for (int j = 3; j >= 0; --j) {
+      lt = lt || (eq && w[j] < r64[j]);
+      eq = eq && (w[j] == r64[j]);
+    }
+    if (lt) break;
+    if (t == 63) {
+      uint64_t b = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint64_t d = w[j] - r64[j] - b;
+        b = (w[j] < r64[j] || (w[j] == r64[j] && b)) ? 1 : 0;
+        w[j] = d;
+      }
+    }
+  }
+  u32x4 a = {(uint32_t)w[0], (uint32_t)(w[0] >> 32), (uint32_t)w[1], (uint32_t)(w[1] >> 32)};
+  u32x4 b = {(uint32_t)w[2], (uint32_t)(w[2] >> 32), (uint32_t)w[3], (uint32_t)(w[3] >> 32)};
+  out[2 * i] = a;
+  out[2 * i + 1] = b;
+}
+
+// Flag any element >= r.
+__global__ void validate_kernel(const u32x4* data, uint64_t count, unsigned int* flag) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const fr_t x = ld_elem(data, (int64_t)i);
+  uint32_t b = 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) subb(x.w[j], fr_mod_word(j), b, &b);
+  if (!b) atomicOr(flag, 1u);
+}
+
+// Zero `n` 32-bit words (used instead of a memset node so that graph
+// captures contain only kernels).
+__global__ void zero_words_kernel(unsigned int* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+}  // namespace frntt

@@ -1,0 +1,219 @@
+// Constant tables of a context, built on the host once and copied to HBM.
+//
+// * twiddles: the paper generates its twiddle matrices offline (Fig. 4
+//   caption) and notes that tables growing with N run out of memory (3-step
+//   NTT, Introduction); here the pass twiddles w_M^e for any M <= 2^28 come
+//   from two 2^14-entry tables of w_{2^28} powers and one extra product;
+//   in-pass twiddles come from one 4096-entry table.
+// * byte-limb constant blocks for the matrix form (Alg. 1, Precomputation:
+//   the BAT-shifted constants I_{i,b} = ... << 8b mod Q and their byte split
+//   E[i,b,j,h]): for a radix rho, block j holds the signed base-256 digits
+//   e_h of w_rho^j * 2^(8a) mod r for a, h in [0, 32).
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <vector>
+
+#include "frntt_internal.hpp"
+#include "host_field.hpp"
+
+namespace frntt {
+
+namespace {
+
+using host::Fe;
+using host::Field;
+
+void put_elem(uint8_t* dst, const Fe& a) { std::memcpy(dst, a.v, 32); }
+
+uint8_t byte_of(const Fe& a, int h) { return (uint8_t)(a.v[h >> 3] >> (8 * (h & 7))); }
+
+// Signed base-256 digits of a canonical value: sum_h e_h 256^h = a, e_h in [-128, 127].
+void signed_digits(const Fe& a, int8_t e[32]) {
+  int carry = 0;
+  for (int h = 0; h < 32; ++h) {
+    int d = byte_of(a, h) + carry;
+    if (d >= 128) {
+      e[h] = (int8_t)(d - 256);
+      carry = 1;
+    } else {
+      e[h] = (int8_t)d;
+      carry = 0;
+    }
+  }
+  // top byte of a value < r is at most 0x30, so the last carry is zero
+}
+
+struct Layout {
+  size_t tw_lo[2], tw_hi[2], w4096[2], g_lo[2], g_hi[2], ninv;
+  size_t bat[2][6], bat_init[2][6];
+  size_t total;
+};
+
+Layout make_layout() {
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return o;
+  };
+  for (int d = 0; d < 2; ++d) {
+    L.tw_lo[d] = take((size_t)32 << kSplit);
+    L.tw_hi[d] = take((size_t)32 << kSplit);
+    L.w4096[d] = take(32 * 4096);
+    L.g_lo[d] = take((size_t)32 << kSplit);
+    L.g_hi[d] = take((size_t)32 << kSplit);
+  }
+  L.ninv = take(32 * 29);
+  for (int d = 0; d < 2; ++d)
+    for (int m = 1; m <= 5; ++m) {
+      L.bat[d][m] = take((size_t)1024 << m);
+      L.bat_init[d][m] = take((size_t)128 << m);
+    }
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+// Builds every table into host memory `h` (layout from make_layout).
+static void fill_tables(uint8_t* h, const Layout& L) {
+  Field F;
+  const Fe one = host::from_u64(1);
+  Fe w28[2];
+  w28[0] = F.root(kMasterLog);
+  w28[1] = F.inv(w28[0]);
+  const Fe g[2] = {host::from_u64(5), F.inv(host::from_u64(5))};
+  for (int d = 0; d < 2; ++d) {
+    // w28^j and w28^(2^14 j)
+    Fe step_hi = F.pow_u64(w28[d], 1ull << kSplit);
+    Fe p = one, q = one;
+    for (int j = 0; j < (1 << kSplit); ++j) {
+      put_elem(h + L.tw_lo[d] + 32 * (size_t)j, F.to_m(p));
+      put_elem(h + L.tw_hi[d] + 32 * (size_t)j, F.to_m(q));
+      p = F.mul(p, w28[d]);
+      q = F.mul(q, step_hi);
+    }
+    // w_4096^j
+    Fe w4096 = F.pow_u64(w28[d], 1ull << (kMasterLog - 12));
+    p = one;
+    for (int j = 0; j < 4096; ++j) {
+      put_elem(h + L.w4096[d] + 32 * (size_t)j, F.to_m(p));
+      p = F.mul(p, w4096);
+    }
+    // g^(+-j) and g^(+-(2^14 j))
+    Fe g_hi_step = F.pow_u64(g[d], 1ull << kSplit);
+    p = one;
+    q = one;
+    for (int j = 0; j < (1 << kSplit); ++j) {
+      put_elem(h + L.g_lo[d] + 32 * (size_t)j, F.to_m(p));
+      put_elem(h + L.g_hi[d] + 32 * (size_t)j, F.to_m(q));
+      p = F.mul(p, g[d]);
+      q = F.mul(q, g_hi_step);
+    }
+  }
+  // 2^-L
+  Fe half = F.inv(host::from_u64(2)), p = one;
+  for (int l = 0; l <= 28; ++l) {
+    put_elem(h + L.ninv + 32 * (size_t)l, F.to_m(p));
+    p = F.mul(p, half);
+  }
+  // bias B = floor(2^275 / r) * r = 2^275 - (2^275 mod r), as 35 bytes
+  // (keeps every merged sum positive; B = 0 mod r)
+  Fe rem = one;
+  for (int i = 0; i < 275; ++i) rem = host::add(rem, rem);
+  uint8_t bias[35];
+  {
+    // 2^275 - rem over 5 limbs
+    uint64_t a[5] = {0, 0, 0, 0, 1ull << (275 - 256)};
+    uint64_t br = 0;
+    for (int i = 0; i < 5; ++i) {
+      unsigned __int128 dd = (unsigned __int128)a[i] - (i < 4 ? rem.v[i] : 0) - br;
+      a[i] = (uint64_t)dd;
+      br = (uint64_t)(dd >> 127);
+    }
+    for (int b = 0; b < 35; ++b) bias[b] = (uint8_t)(a[b >> 3] >> (8 * (b & 7)));
+  }
+  int32_t beta[32];
+  for (int hh = 0; hh < 31; ++hh) beta[hh] = bias[hh];
+  beta[31] = (int32_t)bias[31] | ((int32_t)bias[32] << 8) | ((int32_t)bias[33] << 16) |
+             ((int32_t)bias[34] << 24);
+  // byte-limb blocks per radix
+  for (int d = 0; d < 2; ++d) {
+    for (int m = 1; m <= 5; ++m) {
+      const int rho = 1 << m;
+      const Fe wr = F.pow_u64(w28[d], 1ull << (kMasterLog - m));
+      std::vector<int8_t> dig((size_t)rho * 32 * 32);  // [j][a][h]
+      Fe wj = one;
+      for (int j = 0; j < rho; ++j) {
+        Fe c = wj;
+        for (int a = 0; a < 32; ++a) {
+          signed_digits(c, &dig[((size_t)j * 32 + a) * 32]);
+          c = host::add(c, c);  // *2 eight times = *256
+          for (int s = 0; s < 7; ++s) c = host::add(c, c);
+        }
+        wj = F.mul(wj, wr);
+      }
+      int8_t* blk = (int8_t*)(h + L.bat[d][m]);
+      for (int j = 0; j < rho; ++j)
+        for (int lane = 0; lane < 64; ++lane)
+          for (int i = 0; i < 16; ++i) {
+            const int hh = lane & 31, a = 16 * (lane >> 5) + i;
+            blk[(size_t)j * 1024 + lane * 16 + i] = dig[((size_t)j * 32 + a) * 32 + hh];
+          }
+      int32_t* init = (int32_t*)(h + L.bat_init[d][m]);
+      for (int k = 0; k < rho; ++k) {
+        int32_t S[32] = {0};
+        for (int n = 0; n < rho; ++n) {
+          const int j = (k * n) & (rho - 1);
+          for (int a = 0; a < 32; ++a)
+            for (int hh = 0; hh < 32; ++hh) S[hh] += dig[((size_t)j * 32 + a) * 32 + hh];
+        }
+        for (int half2 = 0; half2 < 2; ++half2)
+          for (int rg = 0; rg < 16; ++rg) {
+            const int hh = 8 * (rg >> 2) + 4 * half2 + (rg & 3);
+            init[(k * 2 + half2) * 16 + rg] = 128 * S[hh] + beta[hh];
+          }
+      }
+    }
+  }
+}
+
+int build_tables(frntt_ctx* ctx) {
+  const Layout L = make_layout();
+  std::vector<uint8_t> h(L.total, 0);
+  fill_tables(h.data(), L);
+  void* dmem = nullptr;
+  hipError_t e = hipMalloc(&dmem, L.total);
+  if (e != hipSuccess) {
+    set_hip_error(ctx, e);
+    return FRNTT_ENOMEM;
+  }
+  e = hipMemcpy(dmem, h.data(), L.total, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    hipFree(dmem);
+    return set_hip_error(ctx, e);
+  }
+  ctx->table_mem = dmem;
+  ctx->table_bytes = L.total;
+  uint8_t* b = (uint8_t*)dmem;
+  DevTables& T = ctx->tables;
+  for (int d = 0; d < 2; ++d) {
+    T.tw_lo[d] = (const u32x4*)(b + L.tw_lo[d]);
+    T.tw_hi[d] = (const u32x4*)(b + L.tw_hi[d]);
+    T.w4096[d] = (const u32x4*)(b + L.w4096[d]);
+    T.g_lo[d] = (const u32x4*)(b + L.g_lo[d]);
+    T.g_hi[d] = (const u32x4*)(b + L.g_hi[d]);
+    T.bat[d][0] = nullptr;
+    T.bat_init[d][0] = nullptr;
+    for (int m = 1; m <= 5; ++m) {
+      T.bat[d][m] = (const i32x4*)(b + L.bat[d][m]);
+      T.bat_init[d][m] = (const i32x4*)(b + L.bat_init[d][m]);
+    }
+  }
+  T.ninv = (const u32x4*)(b + L.ninv);
+  return FRNTT_OK;
+}
+
+}  // namespace frntt

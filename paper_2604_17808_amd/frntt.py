@@ -1,0 +1,253 @@
+"""ctypes binding of libfrntt.so (C ABI declared in include/frntt.h).
+
+Argument marshalling only: every step of every transform runs in the HIP
+library. Device buffers are passed as integer addresses (for example
+``tensor.data_ptr()`` of a torch CUDA/HIP tensor) and streams as integer
+``hipStream_t`` handles (``torch.cuda.current_stream().cuda_stream``; 0 is
+the null stream). If the library has not been built, loading raises: there
+is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(HERE, "libfrntt.so")
+
+FWD, INV, COSET, COSET_INV = 0, 1, 2, 3
+ALGO_AUTO, ALGO_BUTTERFLY, ALGO_FOURSTEP_MFMA = 0, 1, 2
+VALIDATE = 1
+
+OK, EINVAL, ERANGE, EALIGN, ENOMEM, EHIP, EBUSY, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
+
+# Every exported entry point: name -> (restype, argtypes)
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_u64 = ctypes.c_uint64
+_sz = ctypes.c_size_t
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("data", _vp), ("log_n", _i), ("kind", _i)]
+
+
+SIGNATURES = {
+    "frntt_ctx_create": (_i, [ctypes.POINTER(_vp), _i, _i, ctypes.c_uint]),
+    "frntt_ctx_destroy": (_i, [_vp]),
+    "ntt_fwd": (_i, [_vp, _vp, _i, _i, _vp]),
+    "ntt_inv": (_i, [_vp, _vp, _i, _i, _vp]),
+    "ntt_coset": (_i, [_vp, _vp, _i, _i, _vp]),
+    "ntt_coset_inv": (_i, [_vp, _vp, _i, _i, _vp]),
+    "ntt_transform": (_i, [_vp, _vp, _i, _i, _i, _vp]),
+    "ntt_transform_algo": (_i, [_vp, _vp, _i, _i, _i, _i, _vp]),
+    "frntt_set_algo": (_i, [_vp, _i]),
+    "frntt_get_algo": (_i, [_vp]),
+    "frntt_set_plan": (_i, [_vp, _i, _i, ctypes.POINTER(_i), _i]),
+    "frntt_get_plan": (_i, [_vp, _i, _i, ctypes.POINTER(_i), _i]),
+    "ntt_batch": (_i, [_vp, ctypes.POINTER(Job), _i, _vp]),
+    "ntt_batch_graph": (_i, [_vp, ctypes.POINTER(Job), _i, _vp]),
+    "frntt_tune": (_i, [_vp, _i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i),
+                        ctypes.POINTER(ctypes.c_float), _vp]),
+    "frntt_tune_save": (_i, [_vp, ctypes.c_char_p]),
+    "frntt_tune_load": (_i, [_vp, ctypes.c_char_p]),
+    "frntt_generate": (_i, [_vp, _vp, _u64, _u64, _u64, _u64, _vp]),
+    "frntt_check_inputs": (_i, [_vp]),
+    "frntt_scratch_bytes": (_sz, [_i, _i]),
+    "frntt_last_hip_error": (_i, [_vp]),
+    "frntt_strerror": (ctypes.c_char_p, [_i]),
+    "frntt_server_create": (_i, [ctypes.POINTER(_vp), _vp, _sz, _i]),
+    "frntt_server_submit": (_i, [_vp, _i, _i, _u64, ctypes.POINTER(_u64)]),
+    "frntt_server_poll": (_i, [_vp, _u64, ctypes.POINTER(_i), ctypes.POINTER(ctypes.c_double)]),
+    "frntt_server_result": (_i, [_vp, _u64, _vp]),
+    "frntt_server_release": (_i, [_vp, _u64]),
+    "frntt_server_stats": (_i, [_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64),
+                                ctypes.POINTER(_u64)]),
+    "frntt_server_destroy": (_i, [_vp]),
+}
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """Load libfrntt.so (raises if it is missing: build it first)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise FileNotFoundError(
+                f"{_LIB_PATH} is not built; run `python -m paper_2604_17808_amd.build` "
+                "(or __graft_entry__.build())")
+        L = ctypes.CDLL(_LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class FrnttError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        msg = lib().frntt_strerror(status).decode()
+        super().__init__(f"{what}: {msg} ({status})" if what else f"{msg} ({status})")
+        self.status = status
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        raise FrnttError(rc, what)
+    return rc
+
+
+class Context:
+    """A frntt context on one HIP device (owns twiddle tables and scratch)."""
+
+    def __init__(self, device: int = 0, max_log_n: int = 28, flags: int = 0):
+        h = _vp()
+        _check(lib().frntt_ctx_create(ctypes.byref(h), device, max_log_n, flags), "frntt_ctx_create")
+        self._h = h
+        self.device = device
+        self.max_log_n = max_log_n
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().frntt_ctx_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- transforms on raw device addresses
+    def transform(self, ptr: int, log_n: int, batch: int = 1, kind: int = FWD, stream: int = 0,
+                  algo: int | None = None) -> int:
+        if algo is None:
+            rc = lib().ntt_transform(self._h, ptr, log_n, batch, kind, stream)
+        else:
+            rc = lib().ntt_transform_algo(self._h, ptr, log_n, batch, kind, algo, stream)
+        return rc
+
+    def transform_checked(self, ptr, log_n, batch=1, kind=FWD, stream=0, algo=None):
+        return _check(self.transform(ptr, log_n, batch, kind, stream, algo), "ntt_transform")
+
+    def fwd(self, ptr, log_n, batch=1, stream=0):
+        return _check(lib().ntt_fwd(self._h, ptr, log_n, batch, stream), "ntt_fwd")
+
+    def inv(self, ptr, log_n, batch=1, stream=0):
+        return _check(lib().ntt_inv(self._h, ptr, log_n, batch, stream), "ntt_inv")
+
+    def coset(self, ptr, log_n, batch=1, stream=0):
+        return _check(lib().ntt_coset(self._h, ptr, log_n, batch, stream), "ntt_coset")
+
+    def coset_inv(self, ptr, log_n, batch=1, stream=0):
+        return _check(lib().ntt_coset_inv(self._h, ptr, log_n, batch, stream), "ntt_coset_inv")
+
+    def set_algo(self, algo: int):
+        return _check(lib().frntt_set_algo(self._h, algo), "frntt_set_algo")
+
+    def get_algo(self) -> int:
+        return lib().frntt_get_algo(self._h)
+
+    def set_plan(self, algo: int, log_n: int, pass_logs):
+        arr = (_i * max(1, len(pass_logs)))(*pass_logs)
+        return _check(lib().frntt_set_plan(self._h, algo, log_n, arr, len(pass_logs)), "frntt_set_plan")
+
+    def get_plan(self, algo: int, log_n: int):
+        arr = (_i * 4)()
+        n = lib().frntt_get_plan(self._h, algo, log_n, arr, 4)
+        if n < 0:
+            raise FrnttError(n, "frntt_get_plan")
+        return list(arr[:n])
+
+    def batch(self, jobs, stream: int = 0, graph: bool = False):
+        """jobs: iterable of (device address, log_n, kind)."""
+        jobs = list(jobs)
+        arr = (Job * max(1, len(jobs)))(*[Job(p, l, k) for p, l, k in jobs])
+        fn = lib().ntt_batch_graph if graph else lib().ntt_batch
+        return _check(fn(self._h, arr, len(jobs), stream), "ntt_batch")
+
+    def tune(self, log_n: int, batch: int = 1, stream: int = 0):
+        a, p = _i(), _i()
+        ms = ctypes.c_float()
+        _check(lib().frntt_tune(self._h, log_n, batch, ctypes.byref(a), ctypes.byref(p),
+                                ctypes.byref(ms), stream), "frntt_tune")
+        return a.value, p.value, ms.value
+
+    def tune_save(self, path: str):
+        return _check(lib().frntt_tune_save(self._h, path.encode()), "frntt_tune_save")
+
+    def tune_load(self, path: str):
+        return _check(lib().frntt_tune_load(self._h, path.encode()), "frntt_tune_load")
+
+    def generate(self, ptr: int, seed: int, stream_id: int, start: int, count: int, stream: int = 0):
+        return _check(lib().frntt_generate(self._h, ptr, seed, stream_id, start, count, stream),
+                      "frntt_generate")
+
+    def check_inputs(self) -> int:
+        return lib().frntt_check_inputs(self._h)
+
+    def last_hip_error(self) -> int:
+        return lib().frntt_last_hip_error(self._h)
+
+
+class Server:
+    """Continuous-batching request server (see frntt_server_* in include/frntt.h)."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int, slots: int = 4):
+        h = _vp()
+        _check(lib().frntt_server_create(ctypes.byref(h), ctx.handle, hbm_budget_bytes, slots),
+               "frntt_server_create")
+        self._h = h
+        self.ctx = ctx
+
+    def submit(self, kind: int, log_n: int, data_seed: int) -> int:
+        t = _u64()
+        _check(lib().frntt_server_submit(self._h, kind, log_n, data_seed, ctypes.byref(t)),
+               "frntt_server_submit")
+        return t.value
+
+    def poll(self, ticket: int):
+        done = _i()
+        lat = ctypes.c_double()
+        _check(lib().frntt_server_poll(self._h, ticket, ctypes.byref(done), ctypes.byref(lat)),
+               "frntt_server_poll")
+        return bool(done.value), lat.value
+
+    def result(self, ticket: int, host_ptr: int):
+        return _check(lib().frntt_server_result(self._h, ticket, host_ptr), "frntt_server_result")
+
+    def release(self, ticket: int):
+        return _check(lib().frntt_server_release(self._h, ticket), "frntt_server_release")
+
+    def stats(self):
+        c, b, p = _u64(), _u64(), _u64()
+        _check(lib().frntt_server_stats(self._h, ctypes.byref(c), ctypes.byref(b), ctypes.byref(p)),
+               "frntt_server_stats")
+        return {"completed": c.value, "batches": b.value, "peak_bytes": p.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().frntt_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
