@@ -1,0 +1,164 @@
+"""Benchmark: BN254-Fr NTT throughput on one MI355X.
+
+A step is one forward NTT of N = 2^20 seeded uniform field elements (the
+2^20 four-step configuration), timed on the GPU with HIP events on the
+stream the kernels run on, inputs already resident in HBM. The headline
+``value`` is the int8-MFMA limb-matmul form in Melem/s (= N / time); the
+butterfly form, the 2^24 coset round trip, the uneven batch and the oracle
+on host cores are reported beside it.
+
+Prints one JSON line (see the keys below). ``--gpus`` above 1 exits: this
+build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+INT8_PEAK_TOPS = 5000.0        # MI355X dense int8 MFMA, TOP/s
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_transform(ctx, torch, ptr, log_n, batch, kind, algo, steps, warmup, stream):
+    for _ in range(warmup):
+        ctx.transform_checked(ptr, log_n, batch, kind, stream, algo)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ctx.transform_checked(ptr, log_n, batch, kind, stream, algo)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    return times
+
+
+def cpu_baseline(log_n_sample=20, budget_s=20.0):
+    """The C oracle (radix-2, OpenMP) on this host's cores, on 2^20 forward
+    transforms repeated for about `budget_s` seconds."""
+    import numpy as np
+
+    import seeded_inputs as si
+    from oracle import cref
+    x = si.polynomial(2, log_n_sample)
+    threads = cref.max_threads()
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        cref.transform(x, log_n_sample, 0, threads=threads)
+        reps += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = (time.perf_counter() - t0) / reps
+    return {"value": round((1 << log_n_sample) / dt / 1e6, 3), "unit": "Melem/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{reps} forward NTTs of 2^{log_n_sample} (seed 2) with the plain C radix-2 "
+                      f"oracle, OpenMP over {threads} threads, {dt * 1e3:.1f} ms each"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing on host cores")
+    ap.add_argument("--quick", action="store_true", help="headline config only")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2604_17808_amd as fr
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    ctx = fr.Context(0, max_log_n=24)
+    stream = torch.cuda.current_stream().cuda_stream
+    out = {}
+
+    # ---- headline: 2^20 forward, MFMA vs butterfly
+    log_n = 20
+    n = 1 << log_n
+    buf = torch.empty((n, 4), dtype=torch.int64, device="cuda:0")
+    ctx.generate(buf.data_ptr(), 2, 0, 0, n, stream)
+    res = {}
+    for name, algo in (("mfma", fr.ALGO_FOURSTEP_MFMA), ("butterfly", fr.ALGO_BUTTERFLY)):
+        log(f"timing 2^20 forward {name}")
+        t = time_transform(ctx, torch, buf.data_ptr(), log_n, 1, fr.FWD, algo, args.steps, args.warmup,
+                           stream)
+        res[name] = {"ms_median": statistics.median(t), "ms_mean": statistics.fmean(t),
+                     "melem_s": n / (statistics.median(t) * 1e-3) / 1e6, "plan": ctx.get_plan(algo, log_n)}
+    mf = res["mfma"]
+    out["c2"] = res
+
+    if not args.quick:
+        # ---- 2^24 coset NTT then coset INTT (MFMA form), per transform
+        log(f"timing 2^24 coset round trip")
+        n24 = 1 << 24
+        b24 = torch.empty((n24, 4), dtype=torch.int64, device="cuda:0")
+        ctx.generate(b24.data_ptr(), 3, 0, 0, n24, stream)
+        c3 = {}
+        for name, algo in (("mfma", fr.ALGO_FOURSTEP_MFMA), ("butterfly", fr.ALGO_BUTTERFLY)):
+            steps = max(3, args.steps // 5)
+            t_f = time_transform(ctx, torch, b24.data_ptr(), 24, 1, fr.COSET, algo, steps, 2, stream)
+            t_i = time_transform(ctx, torch, b24.data_ptr(), 24, 1, fr.COSET_INV, algo, steps, 2, stream)
+            c3[name] = {"coset_ms": statistics.median(t_f), "coset_inv_ms": statistics.median(t_i),
+                        "melem_s": n24 / (statistics.median(t_f) * 1e-3) / 1e6,
+                        "plan": ctx.get_plan(algo, 24)}
+        out["c3"] = c3
+        del b24
+
+    # ---- roofline of the dominant kernel (the MFMA pass kernel): each of
+    # the two launches of a 2^20 transform reads and writes every element once
+    per_launch_ms = mf["ms_median"] / len(mf["plan"])
+    alg_bytes = 2 * n * 32
+    achieved = alg_bytes / (per_launch_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "ntt_pass_mfma_kernel", "launch_ms": round(per_launch_ms, 5)}
+
+    cpu = None if args.no_cpu else cpu_baseline()
+
+    line = {
+        "metric": "BN254-Fr NTT Melem/s at N=2^20 (int8-MFMA limb-matmul form)",
+        "value": round(mf["melem_s"], 2),
+        "unit": "Melem/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(mf["ms_median"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "single forward NTT, N=2^20, BN254 Fr, uniform seeded coefficients "
+                               "(seed 2), four-step int8-MFMA form, batch 1",
+                   "log_n": 20, "batch": 1, "plan_passes": mf["plan"]},
+        "butterfly_melem_s": round(res["butterfly"]["melem_s"], 2),
+        "mfma_over_butterfly": round(mf["melem_s"] / res["butterfly"]["melem_s"], 3),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "detail": out,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()
