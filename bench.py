@@ -70,6 +70,93 @@ def cpu_baseline(log_n_sample=20, budget_s=20.0):
                       f"oracle, OpenMP over {threads} threads, {dt * 1e3:.1f} ms each"}
 
 
+def bench_c4(ctx, torch, fr, stream, replays):
+    """256 forward NTTs, sizes uniform over 2^12..2^20 (seed 4): tune every
+    size, capture the persistent batch launch in a hipGraph, time replays."""
+    import seeded_inputs as si
+    sizes = si.uneven_batch_sizes(4, 256, 12, 20)
+    tuned = {}
+    for l in sorted(set(sizes)):
+        log(f"c4: tuning 2^{l}")
+        algo, npass, ms = ctx.tune(l, 1, stream)
+        tuned[l] = {"algo": "mfma" if algo == fr.ALGO_FOURSTEP_MFMA else "butterfly",
+                    "passes": ctx.get_plan(fr.ALGO_AUTO, l), "ms": round(ms, 4)}
+    bufs = []
+    for j, l in enumerate(sizes):
+        t = torch.empty((1 << l, 4), dtype=torch.int64, device="cuda:0")
+        ctx.generate(t.data_ptr(), 4, j, 0, 1 << l, stream)
+        bufs.append(t)
+    jobs = [(b.data_ptr(), l, 0) for b, l in zip(bufs, sizes)]
+    log(f"c4: {replays} graph replays")
+    ctx.batch(jobs, stream, graph=True)                    # capture
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(replays):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ctx.batch(jobs, stream, graph=True)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    times.sort()
+    total = sum(1 << l for l in sizes)
+    p50 = times[len(times) // 2]
+    p99 = times[min(len(times) - 1, int(round(0.99 * (len(times) - 1))))]
+    del bufs
+    return {"jobs": 256, "elements": total, "replays": replays, "p50_ms": round(p50, 4),
+            "p99_ms": round(p99, 4), "melem_s_at_p50": round(total / (p50 * 1e-3) / 1e6, 1),
+            "tuned": tuned}
+
+
+def bench_c5(ctx, fr, n_requests):
+    """Poisson arrivals of NTT/INTT/coset-NTT (40/40/20), sizes uniform over
+    2^14..2^22, 64 GiB budget, at 0.5/0.8/0.95 of the measured saturation rate."""
+    import seeded_inputs as si
+    srv = fr.Server(ctx, 64 << 30, slots=4)
+    srv.set_release_on_done(True)            # results stay on the device; only latency is read
+    try:
+        # saturation: a burst of requests with the same size/kind mix
+        burst = si.request_stream(1005, min(2000, n_requests), 14, 22, rate_per_s=1.0)
+        log("c5: warm-up + saturation burst")
+        warm = [srv.submit(r["kind"], r["log_n"], 5) for r in burst[:200]]
+        srv.drain(600)
+        t0 = time.perf_counter()
+        tks = [srv.submit(r["kind"], r["log_n"], 5) for r in burst]
+        srv.drain(600)
+        sat = len(burst) / (time.perf_counter() - t0)
+        res = {"saturation_req_s": round(sat, 1), "requests": n_requests, "budget_gib": 64, "slots": 4}
+        for frac in (0.5, 0.8, 0.95):
+            rate = frac * sat
+            reqs = si.request_stream(5, n_requests, 14, 22, rate_per_s=rate)
+            log(f"c5: {n_requests} requests at {rate:.0f}/s")
+            t0 = time.perf_counter()
+            tks = []
+            for r in reqs:
+                while time.perf_counter() - t0 < r["t_arrive_s"]:
+                    pass
+                tks.append(srv.submit(r["kind"], r["log_n"], 5))
+            srv.drain(600)
+            wall = time.perf_counter() - t0
+            lats = []
+            for tk in tks:
+                done, lat = srv.poll(tk)
+                lats.append(lat)
+            lats.sort()
+            elems = sum(1 << r["log_n"] for r in reqs)
+            res[f"lambda_{frac}"] = {
+                "rate_req_s": round(rate, 1), "p50_ms": round(lats[len(lats) // 2], 3),
+                "p99_ms": round(lats[int(0.99 * (len(lats) - 1))], 3),
+                "throughput_req_s": round(len(reqs) / wall, 1),
+                "throughput_melem_s": round(elems / wall / 1e6, 1)}
+        st = srv.stats()
+        res["batches"] = st["batches"]
+        res["peak_gib"] = round(st["peak_bytes"] / 2**30, 2)
+        return res
+    finally:
+        srv.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +164,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing on host cores")
     ap.add_argument("--quick", action="store_true", help="headline config only")
+    ap.add_argument("--c4-replays", type=int, default=200)
+    ap.add_argument("--serve-requests", type=int, default=10000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
@@ -122,6 +211,10 @@ def main():
                         "plan": ctx.get_plan(algo, 24)}
         out["c3"] = c3
         del b24
+
+    if not args.quick:
+        out["c4"] = bench_c4(ctx, torch, fr, stream, args.c4_replays)
+        out["c5"] = bench_c5(ctx, fr, args.serve_requests)
 
     # ---- roofline of the dominant kernel (the MFMA pass kernel): each of
     # the two launches of a 2^20 transform reads and writes every element once

@@ -183,10 +183,20 @@ int frntt_server_poll(frntt_server *srv, uint64_t ticket, int *done, double *lat
 int frntt_server_result(frntt_server *srv, uint64_t ticket, void *host_out);
 /* Release a finished request's buffer without copying. */
 int frntt_server_release(frntt_server *srv, uint64_t ticket);
+/* Wait up to timeout_s seconds until every submitted request is done.
+ * EBUSY on time-out, or at once if the server is stalled: the queue head
+ * does not fit the budget, nothing is running, and only releasing finished
+ * results (frntt_server_result / frntt_server_release) can make room. */
+int frntt_server_drain(frntt_server *srv, double timeout_s);
+/* on != 0: return a request's buffer to the pool as soon as it completes
+ * (poll still reports its latency; result() then returns ESTATE). For
+ * clients that consume results on the device or only measure latency. */
+int frntt_server_set_release_on_done(frntt_server *srv, int on);
 /* Counters: requests completed, batches launched, peak bytes in flight. */
 int frntt_server_stats(frntt_server *srv, uint64_t *completed, uint64_t *batches,
                        uint64_t *peak_bytes);
-/* Wait for all submitted requests, stop the worker, free everything. */
+/* Cancel requests not yet admitted, wait for running batches, stop the
+ * worker and free everything. */
 int frntt_server_destroy(frntt_server *srv);
 
 #ifdef __cplusplus

@@ -1,0 +1,490 @@
+// Uneven batches (one persistent launch, optionally replayed from a hipGraph)
+// and the autotuner.
+//
+// Batching follows the paper's batch-size study (Ablation Study - Batch
+// Size): many independent polynomials share one launch so that small sizes
+// still fill the machine. Here every job is planned on its own (its pass
+// split and engine come from the context, tuned or default), all passes of
+// all jobs go into one table, and a persistent grid of resident workgroups
+// pulls (pass, workgroup) items in pass order from a device queue. A pass
+// waits for the previous pass of the same job through a per-pass counter.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "frntt_internal.hpp"
+
+namespace frntt {
+
+namespace {
+
+struct BatchBuild {
+  std::vector<PassParams> passes;
+  std::vector<int> pass_job;
+  std::vector<int> pass_dep;
+  std::vector<int64_t> pass_wgs;
+  std::vector<int64_t> item_pass;
+  std::vector<int64_t> item_wg;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct DevLayout {
+  size_t passes, pass_job, pass_dep, pass_wgs, item_pass, item_wg, counters, total;
+};
+
+DevLayout layout_for(size_t np, size_t ni) {
+  DevLayout L;
+  size_t off = 0;
+  L.passes = off;
+  off = align256(off + np * sizeof(PassParams));
+  L.pass_job = off;
+  off = align256(off + np * sizeof(int));
+  L.pass_dep = off;
+  off = align256(off + np * sizeof(int));
+  L.pass_wgs = off;
+  off = align256(off + np * sizeof(int64_t));
+  L.item_pass = off;
+  off = align256(off + ni * sizeof(int64_t));
+  L.item_wg = off;
+  off = align256(off + ni * sizeof(int64_t));
+  L.counters = off;  // [0] queue head, [1..np] done counters
+  off = align256(off + (np + 1) * sizeof(unsigned int));
+  L.total = off;
+  return L;
+}
+
+// Validate the jobs and compute their scratch needs (bytes, per job offset).
+int check_jobs(frntt_ctx* ctx, const frntt_job* jobs, int n_jobs, std::vector<size_t>* scratch_off,
+               size_t* scratch_total) {
+  if (!ctx || n_jobs < 0 || (n_jobs > 0 && !jobs)) return FRNTT_EINVAL;
+  scratch_off->assign((size_t)n_jobs, 0);
+  size_t tot = 0;
+  for (int j = 0; j < n_jobs; ++j) {
+    const frntt_job& jb = jobs[j];
+    if (!jb.data) return FRNTT_EINVAL;
+    if (jb.kind < FRNTT_FWD || jb.kind > FRNTT_COSET_INV) return FRNTT_EINVAL;
+    if (jb.log_n < 0 || jb.log_n > ctx->max_log_n) return FRNTT_ERANGE;
+    if (((uintptr_t)jb.data & 31) != 0) return FRNTT_EALIGN;
+    if (jb.log_n == 0) continue;
+    const int algo = effective_algo(ctx, jb.log_n, FRNTT_ALGO_AUTO);
+    const Plan plan = plan_for(ctx, algo, jb.log_n);
+    (*scratch_off)[j] = tot;
+    tot += scratch_bytes_for(jb.log_n, 1, plan.n_pass);
+  }
+  *scratch_total = tot;
+  return FRNTT_OK;
+}
+
+int build_batch(frntt_ctx* ctx, const frntt_job* jobs, int n_jobs, const std::vector<void*>& scratch,
+                BatchBuild* B) {
+  std::vector<std::vector<int>> job_passes((size_t)n_jobs);
+  int max_pass = 0;
+  for (int j = 0; j < n_jobs; ++j) {
+    const frntt_job& jb = jobs[j];
+    if (jb.log_n == 0) continue;
+    const int algo = effective_algo(ctx, jb.log_n, FRNTT_ALGO_AUTO);
+    const Plan plan = plan_for(ctx, algo, jb.log_n);
+    std::vector<PassParams> pp;
+    if (plan.n_pass > 1 && !scratch[(size_t)j]) return FRNTT_EINVAL;
+    int rc = build_passes(ctx, plan, jb.log_n, 1, jb.kind, jb.data, scratch[(size_t)j], &pp, algo);
+    if (rc) return rc;
+    int prev = -1;
+    for (PassParams& P : pp) {
+      P.xcd_remap = 0;  // the queue decides placement
+      const int idx = (int)B->passes.size();
+      B->passes.push_back(P);
+      B->pass_job.push_back(j);
+      B->pass_dep.push_back(prev);
+      B->pass_wgs.push_back(P.wg_count);
+      job_passes[(size_t)j].push_back(idx);
+      prev = idx;
+    }
+    max_pass = std::max(max_pass, (int)pp.size());
+  }
+  // items in pass order: every first pass, then every second pass, ...
+  // (largest jobs first inside a stage, so long items start early)
+  std::vector<int> order((size_t)n_jobs);
+  for (int j = 0; j < n_jobs; ++j) order[(size_t)j] = j;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return jobs[a].log_n > jobs[b].log_n; });
+  for (int s = 0; s < max_pass; ++s)
+    for (int j : order) {
+      if ((int)job_passes[(size_t)j].size() <= s) continue;
+      const int p = job_passes[(size_t)j][(size_t)s];
+      for (int64_t w = 0; w < B->pass_wgs[(size_t)p]; ++w) {
+        B->item_pass.push_back(p);
+        B->item_wg.push_back(w);
+      }
+    }
+  return FRNTT_OK;
+}
+
+void fill_host(uint8_t* h, const DevLayout& L, const BatchBuild& B) {
+  const size_t np = B.passes.size(), ni = B.item_pass.size();
+  std::memcpy(h + L.passes, B.passes.data(), np * sizeof(PassParams));
+  std::memcpy(h + L.pass_job, B.pass_job.data(), np * sizeof(int));
+  std::memcpy(h + L.pass_dep, B.pass_dep.data(), np * sizeof(int));
+  std::memcpy(h + L.pass_wgs, B.pass_wgs.data(), np * sizeof(int64_t));
+  std::memcpy(h + L.item_pass, B.item_pass.data(), ni * sizeof(int64_t));
+  std::memcpy(h + L.item_wg, B.item_wg.data(), ni * sizeof(int64_t));
+  std::memset(h + L.counters, 0, (np + 1) * sizeof(unsigned int));
+}
+
+BatchParams params_for(uint8_t* d, const DevLayout& L, const BatchBuild& B) {
+  BatchParams P;
+  P.passes = (const PassParams*)(d + L.passes);
+  P.pass_job = (const int*)(d + L.pass_job);
+  P.pass_dep = (const int*)(d + L.pass_dep);
+  P.pass_wgs = (const int64_t*)(d + L.pass_wgs);
+  P.item_pass = (const int64_t*)(d + L.item_pass);
+  P.item_wg = (const int64_t*)(d + L.item_wg);
+  P.n_items = (int64_t)B.item_pass.size();
+  P.queue = (unsigned int*)(d + L.counters);
+  P.done = (unsigned int*)(d + L.counters) + 1;
+  return P;
+}
+
+// Zero the counters and launch the persistent grid (both graph-capturable:
+// kernels only).
+int launch_batch(frntt_ctx* ctx, const BatchParams& P, size_t np, hipStream_t stream) {
+  const int64_t words = (int64_t)np + 1;
+  hipLaunchKernelGGL(zero_words_kernel, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, stream, P.queue,
+                     words);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_hip_error(ctx, e);
+  // one resident workgroup per CU (LDS bound); never more than there are items
+  const int64_t grid = std::min<int64_t>(P.n_items, (int64_t)ctx->cu_count);
+  hipLaunchKernelGGL(ntt_batch_kernel, dim3((unsigned)grid), dim3(kThreads), 0, stream, P, ctx->tables);
+  return set_hip_error(ctx, hipGetLastError());
+}
+
+bool same_jobs(const std::vector<frntt_job>& a, const frntt_job* b, int n) {
+  if ((int)a.size() != n) return false;
+  for (int i = 0; i < n; ++i)
+    if (a[(size_t)i].data != b[i].data || a[(size_t)i].log_n != b[i].log_n || a[(size_t)i].kind != b[i].kind)
+      return false;
+  return true;
+}
+
+}  // namespace
+
+static int batch_launch_common(frntt_ctx* ctx, const frntt_job* jobs, int n_jobs,
+                               const std::vector<void*>& scratch, hipStream_t stream);
+
+int batch_impl(frntt_ctx* ctx, const frntt_job* jobs, int n_jobs, hipStream_t stream) {
+  std::vector<size_t> soff;
+  size_t stot = 0;
+  int rc = check_jobs(ctx, jobs, n_jobs, &soff, &stot);
+  if (rc) return rc;
+  if (n_jobs == 0) return FRNTT_OK;
+  void* base = nullptr;
+  rc = get_scratch(ctx, stream, stot, &base);
+  if (rc) return rc;
+  std::vector<void*> scratch((size_t)n_jobs, nullptr);
+  for (int j = 0; j < n_jobs; ++j) scratch[(size_t)j] = base ? (uint8_t*)base + soff[(size_t)j] : nullptr;
+  return batch_launch_common(ctx, jobs, n_jobs, scratch, stream);
+}
+
+// As batch_impl with caller-provided scratch per job (NULL for single-pass
+// sizes); used by the server, whose request buffers carry their scratch.
+int batch_impl_ws(frntt_ctx* ctx, const frntt_job* jobs, void* const* scratch_in, int n_jobs, hipStream_t stream) {
+  std::vector<size_t> soff;
+  size_t stot = 0;
+  int rc = check_jobs(ctx, jobs, n_jobs, &soff, &stot);
+  if (rc) return rc;
+  if (n_jobs == 0) return FRNTT_OK;
+  std::vector<void*> scratch(scratch_in, scratch_in + n_jobs);
+  return batch_launch_common(ctx, jobs, n_jobs, scratch, stream);
+}
+
+static int batch_launch_common(frntt_ctx* ctx, const frntt_job* jobs, int n_jobs,
+                               const std::vector<void*>& scratch, hipStream_t stream) {
+  int rc;
+  BatchBuild B;
+  rc = build_batch(ctx, jobs, n_jobs, scratch, &B);
+  if (rc) return rc;
+  if (B.item_pass.empty()) return FRNTT_OK;
+  const DevLayout L = layout_for(B.passes.size(), B.item_pass.size());
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  BatchBuffers& bb = ctx->batch_bufs[stream];
+  // the previous batch on this stream may still read the buffers: wait for
+  // its upload to finish before reusing the host staging, and keep the device
+  // buffer stream-ordered
+  if (bb.event) {
+    hipError_t e = hipEventSynchronize(bb.event);
+    if (e != hipSuccess) return set_hip_error(ctx, e);
+  } else if (hipEventCreateWithFlags(&bb.event, hipEventDisableTiming) != hipSuccess) {
+    return FRNTT_EHIP;
+  }
+  if (bb.host_bytes < L.total) {
+    if (bb.host) hipHostFree(bb.host);
+    bb.host = nullptr;
+    bb.host_bytes = 0;
+    if (hipHostMalloc(&bb.host, L.total, 0) != hipSuccess) return FRNTT_ENOMEM;
+    bb.host_bytes = L.total;
+  }
+  if (bb.dev_bytes < L.total) {
+    if (bb.dev) {
+      hipError_t e = hipStreamSynchronize(stream);
+      if (e != hipSuccess) return set_hip_error(ctx, e);
+      hipFree(bb.dev);
+    }
+    bb.dev = nullptr;
+    bb.dev_bytes = 0;
+    if (hipMalloc(&bb.dev, L.total) != hipSuccess) return FRNTT_ENOMEM;
+    bb.dev_bytes = L.total;
+  }
+  fill_host((uint8_t*)bb.host, L, B);
+  hipError_t e = hipMemcpyAsync(bb.dev, bb.host, L.total, hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return set_hip_error(ctx, e);
+  e = hipEventRecord(bb.event, stream);
+  if (e != hipSuccess) return set_hip_error(ctx, e);
+  const BatchParams P = params_for((uint8_t*)bb.dev, L, B);
+  return launch_batch(ctx, P, B.passes.size(), stream);
+}
+
+int batch_graph_impl(frntt_ctx* ctx, const frntt_job* jobs, int n_jobs, hipStream_t stream) {
+  std::vector<size_t> soff;
+  size_t stot = 0;
+  int rc = check_jobs(ctx, jobs, n_jobs, &soff, &stot);
+  if (rc) return rc;
+  if (n_jobs == 0) return FRNTT_OK;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (GraphEntry& g : ctx->graphs)
+      if (same_jobs(g.jobs, jobs, n_jobs)) {
+        hipError_t e = hipGraphLaunch(g.exec, stream);
+        return set_hip_error(ctx, e);
+      }
+  }
+  // new entry: dedicated scratch and descriptors, captured once
+  GraphEntry g;
+  g.jobs.assign(jobs, jobs + n_jobs);
+  hipError_t e;
+  if (stot) {
+    e = hipMalloc(&g.scratch, stot);
+    if (e != hipSuccess) return FRNTT_ENOMEM;
+  }
+  BatchBuild B;
+  std::vector<void*> scratch((size_t)n_jobs, nullptr);
+  for (int j = 0; j < n_jobs; ++j) scratch[(size_t)j] = g.scratch ? (uint8_t*)g.scratch + soff[(size_t)j] : nullptr;
+  rc = build_batch(ctx, jobs, n_jobs, scratch, &B);
+  if (rc) {
+    if (g.scratch) hipFree(g.scratch);
+    return rc;
+  }
+  const DevLayout L = layout_for(B.passes.size(), B.item_pass.size());
+  std::vector<uint8_t> host(L.total);
+  fill_host(host.data(), L, B);
+  e = hipMalloc(&g.dev_buf, L.total);
+  if (e != hipSuccess) {
+    if (g.scratch) hipFree(g.scratch);
+    return FRNTT_ENOMEM;
+  }
+  e = hipMemcpy(g.dev_buf, host.data(), L.total, hipMemcpyHostToDevice);
+  hipStream_t cap = nullptr;
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    const BatchParams P = params_for((uint8_t*)g.dev_buf, L, B);
+    rc = launch_batch(ctx, P, B.passes.size(), cap);
+    hipError_t e2 = hipStreamEndCapture(cap, &g.graph);
+    if (rc == FRNTT_OK && e2 != hipSuccess) e = e2;
+    if (rc != FRNTT_OK && e == hipSuccess) e = hipErrorUnknown;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+  if (cap) hipStreamDestroy(cap);
+  if (e != hipSuccess) {
+    if (g.exec) hipGraphExecDestroy(g.exec);
+    if (g.graph) hipGraphDestroy(g.graph);
+    hipFree(g.dev_buf);
+    if (g.scratch) hipFree(g.scratch);
+    return set_hip_error(ctx, e);
+  }
+  e = hipGraphLaunch(g.exec, stream);
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->graphs.push_back(g);
+  return set_hip_error(ctx, e);
+}
+
+// ---------------------------------------------------------------- tuning
+
+namespace {
+
+void candidate_splits(int log_n, std::vector<std::vector<int>>* out) {
+  out->clear();
+  if (log_n <= 12) out->push_back({log_n});
+  for (int a = 1; a <= 12; ++a) {
+    const int b = log_n - a;
+    if (b >= 1 && b <= 12 && a >= 4 && b >= 4) out->push_back({a, b});
+  }
+  if (log_n >= 15)
+    for (int a = 5; a <= 12; ++a)
+      for (int b = 5; b <= 12; ++b) {
+        const int c = log_n - a - b;
+        if (c >= 5 && c <= 12 && std::abs(a - b) <= 2 && std::abs(b - c) <= 2) out->push_back({a, b, c});
+      }
+}
+
+}  // namespace
+
+int tune_impl(frntt_ctx* ctx, int log_n, int batch, int* best_algo, int* best_passes, float* best_ms,
+              hipStream_t stream) {
+  if (!ctx || batch < 1) return FRNTT_EINVAL;
+  if (log_n < 1 || log_n > ctx->max_log_n) return FRNTT_ERANGE;
+  const size_t count = (size_t)batch << log_n;
+  void* buf = nullptr;
+  if (hipMalloc(&buf, count * 32) != hipSuccess) return FRNTT_ENOMEM;
+  int rc = frntt_generate(ctx, buf, 7, 0, 0, count, stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  std::vector<std::vector<int>> splits;
+  candidate_splits(log_n, &splits);
+  TuneEntry best;
+  best.ms = 1e30f;
+  bool found = false;
+  // the tuner owns the overrides while it runs
+  Plan saved[3];
+  bool saved_has[3];
+  for (int a = 1; a <= 2; ++a) {
+    saved[a] = ctx->plan_override[a][log_n];
+    saved_has[a] = ctx->has_override[a][log_n];
+  }
+  for (int algo = FRNTT_ALGO_BUTTERFLY; rc == FRNTT_OK && algo <= FRNTT_ALGO_FOURSTEP_MFMA; ++algo) {
+    for (const auto& sp : splits) {
+      rc = frntt_set_plan(ctx, algo, log_n, sp.data(), (int)sp.size());
+      if (rc) break;
+      // warm-up, then the median of 3
+      rc = transform_impl(ctx, buf, log_n, batch, FRNTT_FWD, algo, stream, nullptr, 0);
+      if (rc) break;
+      float t[3];
+      for (int r = 0; r < 3 && rc == FRNTT_OK; ++r) {
+        hipEventRecord(e0, stream);
+        rc = transform_impl(ctx, buf, log_n, batch, FRNTT_FWD, algo, stream, nullptr, 0);
+        hipEventRecord(e1, stream);
+        hipEventSynchronize(e1);
+        hipEventElapsedTime(&t[r], e0, e1);
+      }
+      if (rc) break;
+      std::sort(t, t + 3);
+      if (t[1] < best.ms) {
+        best.ms = t[1];
+        best.algo = algo;
+        best.n_pass = (int)sp.size();
+        for (int i = 0; i < 4; ++i) best.pass_log[i] = i < (int)sp.size() ? sp[(size_t)i] : 0;
+        found = true;
+      }
+    }
+  }
+  for (int a = 1; a <= 2; ++a) {
+    ctx->plan_override[a][log_n] = saved[a];
+    ctx->has_override[a][log_n] = saved_has[a];
+  }
+  hipStreamSynchronize(stream);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipFree(buf);
+  if (rc) return rc;
+  if (!found) return FRNTT_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->tuned[log_n] = best;
+    ctx->has_tuned[log_n] = true;
+  }
+  if (best_algo) *best_algo = best.algo;
+  if (best_passes) *best_passes = best.n_pass;
+  if (best_ms) *best_ms = best.ms;
+  return FRNTT_OK;
+}
+
+int tune_save_impl(const frntt_ctx* ctx, const char* path) {
+  if (!ctx || !path) return FRNTT_EINVAL;
+  FILE* f = std::fopen(path, "w");
+  if (!f) return FRNTT_EINVAL;
+  std::fprintf(f, "{\"format\": \"frntt-tune-1\", \"entries\": [");
+  bool first = true;
+  for (int l = 0; l <= 28; ++l) {
+    if (!ctx->has_tuned[l]) continue;
+    const TuneEntry& t = ctx->tuned[l];
+    std::fprintf(f, "%s\n  {\"log_n\": %d, \"algo\": %d, \"passes\": [", first ? "" : ",", l, t.algo);
+    for (int i = 0; i < t.n_pass; ++i) std::fprintf(f, "%s%d", i ? ", " : "", t.pass_log[i]);
+    std::fprintf(f, "], \"ms\": %.6f}", t.ms);
+    first = false;
+  }
+  std::fprintf(f, "\n]}\n");
+  std::fclose(f);
+  return FRNTT_OK;
+}
+
+int tune_load_impl(frntt_ctx* ctx, const char* path) {
+  if (!ctx || !path) return FRNTT_EINVAL;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return FRNTT_EINVAL;
+  std::string s;
+  char buf[4096];
+  size_t n;
+  while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) s.append(buf, n);
+  std::fclose(f);
+  if (s.find("\"frntt-tune-1\"") == std::string::npos) return FRNTT_EINVAL;
+  size_t pos = 0;
+  int loaded = 0;
+  while ((pos = s.find("{\"log_n\":", pos)) != std::string::npos) {
+    int l = -1, algo = 0, p[4] = {0, 0, 0, 0};
+    float ms = 0;
+    const char* c = s.c_str() + pos;
+    int np = std::sscanf(c, "{\"log_n\": %d, \"algo\": %d, \"passes\": [%d, %d, %d, %d", &l, &algo, &p[0], &p[1],
+                         &p[2], &p[3]);
+    if (np < 3 || l < 1 || l > 28 || algo < 1 || algo > 2) return FRNTT_EINVAL;
+    const size_t close = s.find(']', pos);
+    const size_t msp = s.find("\"ms\":", pos);
+    if (msp != std::string::npos) std::sscanf(s.c_str() + msp, "\"ms\": %f", &ms);
+    TuneEntry t;
+    t.algo = algo;
+    t.n_pass = np - 2;
+    // count the entries actually inside the brackets
+    int cnt = 1;
+    for (size_t i = s.find('[', pos); i < close; ++i) cnt += s[i] == ',';
+    t.n_pass = std::min(cnt, 4);
+    for (int i = 0; i < 4; ++i) t.pass_log[i] = i < t.n_pass ? p[i] : 0;
+    t.ms = ms;
+    Plan check;
+    check.n_pass = t.n_pass;
+    for (int i = 0; i < 4; ++i) check.pass_log[i] = t.pass_log[i];
+    if (check_plan_valid(check, l) != FRNTT_OK) return FRNTT_EINVAL;
+    ctx->tuned[l] = t;
+    ctx->has_tuned[l] = true;
+    ++loaded;
+    pos = close;
+  }
+  return loaded > 0 ? FRNTT_OK : FRNTT_EINVAL;
+}
+
+}  // namespace frntt
+
+using namespace frntt;
+
+extern "C" {
+
+int ntt_batch(frntt_ctx* ctx, const frntt_job* jobs, int n_jobs, void* stream) {
+  return batch_impl(ctx, jobs, n_jobs, (hipStream_t)stream);
+}
+
+int ntt_batch_graph(frntt_ctx* ctx, const frntt_job* jobs, int n_jobs, void* stream) {
+  return batch_graph_impl(ctx, jobs, n_jobs, (hipStream_t)stream);
+}
+
+int frntt_tune(frntt_ctx* ctx, int log_n, int batch, int* best_algo, int* best_passes, float* best_ms,
+               void* stream) {
+  return tune_impl(ctx, log_n, batch, best_algo, best_passes, best_ms, (hipStream_t)stream);
+}
+
+int frntt_tune_save(const frntt_ctx* ctx, const char* path) { return tune_save_impl(ctx, path); }
+
+int frntt_tune_load(frntt_ctx* ctx, const char* path) { return tune_load_impl(ctx, path); }
+
+}  // extern "C"

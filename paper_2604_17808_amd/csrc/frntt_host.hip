@@ -305,8 +305,6 @@ int frntt_ctx_create(frntt_ctx** out, int hip_device, int max_log_n, unsigned fl
     if (e != hipSuccess) rc = FRNTT_ENOMEM;
     else if (hipMemset(ctx->valid_flag, 0, 256) != hipSuccess) rc = FRNTT_EHIP;
   }
-  if (rc == FRNTT_OK && hipEventCreateWithFlags(&ctx->batch_host_event, hipEventDisableTiming) != hipSuccess)
-    rc = FRNTT_EHIP;
   if (rc != FRNTT_OK) {
     frntt_ctx_destroy(ctx);
     return rc;
@@ -326,10 +324,13 @@ int frntt_ctx_destroy(frntt_ctx* ctx) {
       if (g.exec) hipGraphExecDestroy(g.exec);
       if (g.graph) hipGraphDestroy(g.graph);
       if (g.dev_buf) hipFree(g.dev_buf);
+      if (g.scratch) hipFree(g.scratch);
     }
-    if (ctx->batch_buf) hipFree(ctx->batch_buf);
-    if (ctx->batch_host) hipHostFree(ctx->batch_host);
-    if (ctx->batch_host_event) hipEventDestroy(ctx->batch_host_event);
+    for (auto& kv : ctx->batch_bufs) {
+      if (kv.second.dev) hipFree(kv.second.dev);
+      if (kv.second.host) hipHostFree(kv.second.host);
+      if (kv.second.event) hipEventDestroy(kv.second.event);
+    }
     if (ctx->valid_flag) hipFree(ctx->valid_flag);
     if (ctx->table_mem) hipFree(ctx->table_mem);
   }

@@ -39,7 +39,16 @@ struct GraphEntry {
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   void* dev_buf = nullptr;  // descriptors + counters used by the captured launch
-  hipStream_t stream = nullptr;
+  void* scratch = nullptr;  // scratch owned by the captured launch
+};
+
+// Per-stream descriptor buffers of ntt_batch.
+struct BatchBuffers {
+  void* dev = nullptr;
+  size_t dev_bytes = 0;
+  void* host = nullptr;     // pinned staging
+  size_t host_bytes = 0;
+  hipEvent_t event = nullptr;  // recorded after the upload from `host`
 };
 
 struct TuneEntry {
@@ -70,11 +79,7 @@ struct frntt_ctx {
   std::mutex mu;                   // guards scratch, graphs, tuning state
   std::map<hipStream_t, frntt::Scratch> scratch;
   std::vector<frntt::GraphEntry> graphs;
-  void* batch_buf = nullptr;       // device descriptors for ntt_batch
-  size_t batch_buf_bytes = 0;
-  void* batch_host = nullptr;      // pinned staging for descriptors
-  size_t batch_host_bytes = 0;
-  hipEvent_t batch_host_event = nullptr;  // marks when batch_host may be reused
+  std::map<hipStream_t, frntt::BatchBuffers> batch_bufs;
 };
 
 namespace frntt {

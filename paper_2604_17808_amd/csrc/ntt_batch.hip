@@ -8,36 +8,48 @@ namespace frntt {
 __global__ __launch_bounds__(kThreads) void ntt_batch_kernel(BatchParams B, DevTables T) {
   __shared__ u32x4 lds[2 << kMaxLogT];
   __shared__ i32x4 lds_f[kBatMaxRho * 64];
-  __shared__ int64_t item_sh;
+  __shared__ int item_sh;
+  // The loop skeleton has no lane-divergent branches: the queue and counter
+  // atomics are issued by all 64 lanes of wave 0 (lane 0 adds 1, the others
+  // 0) and every loop condition is made wave-uniform with readfirstlane.
+  // A thread-0-only block at the end of a loop that contains barriers lets
+  // the compiler restructure the loop around lane 0, and the barriers then
+  // no longer pair up.
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const unsigned int one = (threadIdx.x & 63) == 0 ? 1u : 0u;
   for (;;) {
-    if (threadIdx.x == 0) item_sh = (int64_t)atomicAdd(B.queue, 1u);
+    if (wave == 0) item_sh = (int)__builtin_amdgcn_readfirstlane(atomicAdd(B.queue, one));
     __syncthreads();
-    const int64_t item = item_sh;
+    const int64_t item = __builtin_amdgcn_readfirstlane(item_sh);
     __syncthreads();
     if (item >= B.n_items) break;
-    const int64_t p = B.item_pass[item];
-    const int dep = B.pass_dep[p];
+    const int p = __builtin_amdgcn_readfirstlane((int)B.item_pass[item]);
+    const int dep = __builtin_amdgcn_readfirstlane(B.pass_dep[p]);
     if (dep >= 0) {
       // items are handed out pass by pass, so every workgroup of `dep` was
       // taken by a running workgroup before this one: the wait always ends
-      if (threadIdx.x == 0) {
-        const unsigned int need = (unsigned int)B.pass_wgs[dep];
-        while (__hip_atomic_load(&B.done[dep], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need)
+      if (wave == 0) {
+        const unsigned int need = (unsigned int)__builtin_amdgcn_readfirstlane((int)B.pass_wgs[dep]);
+        for (;;) {
+          const unsigned int d = (unsigned int)__builtin_amdgcn_readfirstlane(
+              (int)__hip_atomic_load(&B.done[dep], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+          if (d >= need) break;
           __builtin_amdgcn_s_sleep(2);
+        }
       }
       __syncthreads();
     }
     // every thread reads the pass descriptor straight from global memory
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const PassParams& P = B.passes[p];
-    run_pass<2>(lds, lds_f, P, T, B.item_wg[item]);
+    const int64_t wg = B.item_wg[item];
+    run_pass<2>(lds, lds_f, P, T, wg);
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (wave == 0) {
       __threadfence();
-      __hip_atomic_fetch_add(&B.done[p], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&B.done[p], one, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }
-
 
 }  // namespace frntt

@@ -61,6 +61,8 @@ SIGNATURES = {
     "frntt_server_poll": (_i, [_vp, _u64, ctypes.POINTER(_i), ctypes.POINTER(ctypes.c_double)]),
     "frntt_server_result": (_i, [_vp, _u64, _vp]),
     "frntt_server_release": (_i, [_vp, _u64]),
+    "frntt_server_drain": (_i, [_vp, ctypes.c_double]),
+    "frntt_server_set_release_on_done": (_i, [_vp, _i]),
     "frntt_server_stats": (_i, [_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64),
                                 ctypes.POINTER(_u64)]),
     "frntt_server_destroy": (_i, [_vp]),
@@ -234,6 +236,13 @@ class Server:
 
     def release(self, ticket: int):
         return _check(lib().frntt_server_release(self._h, ticket), "frntt_server_release")
+
+    def drain(self, timeout_s: float = 600.0):
+        return _check(lib().frntt_server_drain(self._h, timeout_s), "frntt_server_drain")
+
+    def set_release_on_done(self, on: bool = True):
+        return _check(lib().frntt_server_set_release_on_done(self._h, 1 if on else 0),
+                      "frntt_server_set_release_on_done")
 
     def stats(self):
         c, b, p = _u64(), _u64(), _u64()
