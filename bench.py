@@ -165,6 +165,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing on host cores")
     ap.add_argument("--quick", action="store_true", help="headline config only")
     ap.add_argument("--c4-replays", type=int, default=200)
+    ap.add_argument("--calib", action="store_true",
+                    help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
     ap.add_argument("--serve-requests", type=int, default=10000)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -179,6 +181,15 @@ def main():
     ctx = fr.Context(0, max_log_n=24)
     stream = torch.cuda.current_stream().cuda_stream
     out = {}
+
+    if args.calib:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give
+        # the scale factor for the transform kernels' counters
+        a = torch.zeros(256 << 20, dtype=torch.uint8, device="cuda:0")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     # ---- headline: 2^20 forward, MFMA vs butterfly
     log_n = 20

@@ -86,7 +86,19 @@ __device__ FRNTT_INLINE fr_t fr_sub(const fr_t& a, const fr_t& b) {
   return o;
 }
 
+// x + y as a 64-bit value (carry in the high word). Written with an explicit
+// add-with-carry so the pair feeds v_mad_u64_u32 directly, without
+// zero-extension moves.
+__device__ FRNTT_INLINE uint64_t add_2x32(uint32_t x, uint32_t y) {
+  uint32_t carry;
+  const uint32_t lo = __builtin_addc(x, y, 0u, &carry);
+  return ((uint64_t)carry << 32) | lo;
+}
+
 // Montgomery product a*b*2^-256 mod r for a, b < r; result canonical.
+// Row i adds a*b_i and m*r with m chosen to clear the low word, then shifts
+// one word; the two carry chains of a row are interleaved (A for a*b_i, C
+// for m*r), each step one 32x32+64 multiply-add.
 __device__ FRNTT_INLINE fr_t mont_mul(const fr_t& a, const fr_t& b) {
   uint32_t t[8];
 #pragma unroll
@@ -95,16 +107,15 @@ __device__ FRNTT_INLINE fr_t mont_mul(const fr_t& a, const fr_t& b) {
   for (int i = 0; i < 8; ++i) {
     uint64_t p = (uint64_t)a.w[0] * b.w[i] + t[0];
     uint32_t A = (uint32_t)(p >> 32);
-    uint32_t t0 = (uint32_t)p;
-    uint32_t m = t0 * FR_NPRIME;
+    const uint32_t t0 = (uint32_t)p;
+    const uint32_t m = t0 * FR_NPRIME;
     uint64_t q = (uint64_t)m * FR_R0 + t0;
     uint32_t C = (uint32_t)(q >> 32);
 #pragma unroll
     for (int j = 1; j < 8; ++j) {
-      p = (uint64_t)a.w[j] * b.w[i] + t[j] + A;
+      p = (uint64_t)a.w[j] * b.w[i] + add_2x32(t[j], A);
       A = (uint32_t)(p >> 32);
-      uint32_t tj = (uint32_t)p;
-      q = (uint64_t)m * fr_mod_word(j) + tj + C;
+      q = (uint64_t)m * fr_mod_word(j) + add_2x32((uint32_t)p, C);
       C = (uint32_t)(q >> 32);
       t[j - 1] = (uint32_t)q;
     }

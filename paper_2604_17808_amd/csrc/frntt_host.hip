@@ -47,7 +47,7 @@ static int split_levels(int l, int max_m, int* out) {
 bool mfma_level_ok(int m, int log_t) {
   if (m < 1 || m > 4) return false;
   const int tiles_log = log_t - m - 5;
-  if (tiles_log < 3) return false;  // 8 waves
+  if (tiles_log < 3) return false;    // 8 waves, at least one tile each
   const int tpw_log = tiles_log - 3;
   return tpw_log + m <= 4;
 }
@@ -58,13 +58,18 @@ bool mfma_level_ok(int m, int log_t) {
 static bool plan_levels(Plan& plan, int p, int log_t_pass) {
   const int l = plan.pass_log[p];
   int levs[kMaxLevels];
-  const int n = split_levels(l, 4, levs);
-  plan.nlev[p] = n;
+  // fewest levels first (each costs a carry merge and a twiddle product)
+  const int max_m = 4;
+  int n = split_levels(l, max_m, levs);
   bool ok = n <= kMaxLevels;
-  for (int i = 0; i < n; ++i) {
-    plan.lev_log[p][i] = levs[i];
-    ok = ok && mfma_level_ok(levs[i], log_t_pass);
+  for (int i = 0; i < n; ++i) ok = ok && mfma_level_ok(levs[i], log_t_pass);
+  if (!ok && max_m == 5) {
+    n = split_levels(l, 4, levs);
+    ok = n <= kMaxLevels;
+    for (int i = 0; i < n; ++i) ok = ok && mfma_level_ok(levs[i], log_t_pass);
   }
+  plan.nlev[p] = n;
+  for (int i = 0; i < n; ++i) plan.lev_log[p][i] = levs[i];
   return ok;
 }
 

@@ -7,8 +7,10 @@ namespace frntt {
 
 __global__ __launch_bounds__(kThreads) void ntt_batch_kernel(BatchParams B, DevTables T) {
   __shared__ u32x4 lds[2 << kMaxLogT];
-  __shared__ i32x4 lds_f[kBatMaxRho * 64];
-  __shared__ int item_sh;
+  __shared__ i32x4 lds_f[kBatMaxRho * 64 + kBatMaxRho * 8];
+  // the item slot shares the constant-block area: it is written and read
+  // only between passes, when no MFMA level uses that area
+  int& item_sh = *reinterpret_cast<int*>(&lds_f[0]);
   // The loop skeleton has no lane-divergent branches: the queue and counter
   // atomics are issued by all 64 lanes of wave 0 (lane 0 adds 1, the others
   // 0) and every loop condition is made wave-uniform with readfirstlane.

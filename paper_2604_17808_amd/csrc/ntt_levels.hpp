@@ -25,7 +25,7 @@
 
 namespace frntt {
 
-constexpr int kBatMaxRho = 16;  // largest MFMA level radix; blocks staged in LDS
+constexpr int kBatMaxRho = 16;  // largest MFMA level radix; blocks staged in LDS (16 KiB)
 
 // ---------------------------------------------------------------- LDS
 
@@ -85,13 +85,16 @@ __device__ FRNTT_INLINE void store_lines(const u32x4* lds, const PassParams& P, 
   const int T_el = 1 << P.log_t;
   const int G = 1 << P.log_g;
   const int tid = threadIdx.x;
+  // two elements in flight per thread: their table loads overlap
+#pragma unroll 2
   for (int e = tid; e < T_el; e += kThreads) {
     const int k = e >> P.log_g, line = e & (G - 1);
     const int row = bitrev ? (int)(__builtin_bitreverse32((uint32_t)k) >> (32 - P.log_r)) : k;
     fr_t y = lds_ld(lds, row * G + line);
     const LineMap mp = map_line(P, wg * G + line);
     if (!P.is_last) {
-      y = mont_mul(y, pow_tw(T, P.dir, P.log_r + P.log_s, (uint64_t)mp.rest * (uint64_t)k));
+      // y may be below 2^256 but not reduced (MFMA engine): word-scanned operand
+      y = mont_mul(pow_tw(T, P.dir, P.log_r + P.log_s, (uint64_t)mp.rest * (uint64_t)k), y);
     } else if (P.post == 1) {
       y = mont_mul(y, ld_elem(T.ninv, P.log_n));
     } else if (P.post == 2) {
@@ -161,49 +164,47 @@ __device__ FRNTT_INLINE void cond_sub_words(uint32_t* y, bool twice) {
 // Merge the byte-plane partials of two outputs (acc0 -> output k0 in lanes
 // 0..31, acc1 -> k1 in lanes 32..63) and reduce mod r. Lane l holds rows
 // h = 8i + 4*(l/32) + j in register 4i + j (the 32x32 MFMA accumulator
-// layout); after the swap of the two half-waves each lane holds all 32
-// partials of its own output: y = sum_h P_h 2^(8h).
-__device__ FRNTT_INLINE fr_t merge_reduce(const i32x16& a0, const i32x16& a1) {
-  int64_t s0[4], s1[4];
+// layout), i.e. the partials of 32-bit words 2i + l/32. After the swap of
+// the two half-waves each lane holds all 32 partials of its own output,
+// y = sum_h P_h 2^(8h) (a multiple of r keeps it positive, below 2^276).
+//
+// The merge runs on exact fp64 integers: a word group sum_j P_(4w+j) 2^(8j)
+// stays below 2^53, and splitting t into floor(t / 2^32) and the remainder
+// is exact. A quotient estimate from the top 52 bits, at most 2 below
+// floor(y / r), then brings y into [0, 3r); `canonical` finishes in [0, r).
+__device__ FRNTT_INLINE fr_t merge_reduce(const i32x16& a0, const i32x16& a1, bool canonical) {
+  double w0[4], w1[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    s0[i] = (int64_t)a0[4 * i] + (int64_t)a0[4 * i + 1] * 256 + (int64_t)a0[4 * i + 2] * 65536 +
-            (int64_t)a0[4 * i + 3] * 16777216;
-    s1[i] = (int64_t)a1[4 * i] + (int64_t)a1[4 * i + 1] * 256 + (int64_t)a1[4 * i + 2] * 65536 +
-            (int64_t)a1[4 * i + 3] * 16777216;
+    w0[i] = __builtin_fma((double)a0[4 * i + 3], 16777216.0,
+             __builtin_fma((double)a0[4 * i + 2], 65536.0,
+              __builtin_fma((double)a0[4 * i + 1], 256.0, (double)a0[4 * i])));
+    w1[i] = __builtin_fma((double)a1[4 * i + 3], 16777216.0,
+             __builtin_fma((double)a1[4 * i + 2], 65536.0,
+              __builtin_fma((double)a1[4 * i + 1], 256.0, (double)a1[4 * i])));
   }
-  int64_t X[4], Y[4];
+  double X[4], Y[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)s0[i], (uint32_t)s1[i], false, false);
-    auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)((uint64_t)s0[i] >> 32),
-                                               (uint32_t)((uint64_t)s1[i] >> 32), false, false);
-    X[i] = (int64_t)(((uint64_t)hi[0] << 32) | (uint32_t)lo[0]);
-    Y[i] = (int64_t)(((uint64_t)hi[1] << 32) | (uint32_t)lo[1]);
+    const uint64_t b0 = __builtin_bit_cast(uint64_t, w0[i]);
+    const uint64_t b1 = __builtin_bit_cast(uint64_t, w1[i]);
+    auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)b0, (uint32_t)b1, false, false);
+    auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(b0 >> 32), (uint32_t)(b1 >> 32), false, false);
+    X[i] = __builtin_bit_cast(double, ((uint64_t)hi[0] << 32) | (uint32_t)lo[0]);  // word 2i
+    Y[i] = __builtin_bit_cast(double, ((uint64_t)hi[1] << 32) | (uint32_t)lo[1]);  // word 2i + 1
   }
   uint32_t y[9];
-  int64_t t = X[0];
-  y[0] = (uint32_t)t;
-  t = Y[0] + (t >> 32);
-  y[1] = (uint32_t)t;
-  t = X[1] + (t >> 32);
-  y[2] = (uint32_t)t;
-  t = Y[1] + (t >> 32);
-  y[3] = (uint32_t)t;
-  t = X[2] + (t >> 32);
-  y[4] = (uint32_t)t;
-  t = Y[2] + (t >> 32);
-  y[5] = (uint32_t)t;
-  t = X[3] + (t >> 32);
-  y[6] = (uint32_t)t;
-  t = Y[3] + (t >> 32);
-  y[7] = (uint32_t)t;
-  y[8] = (uint32_t)(t >> 32);  // value is positive (bias) and < 2^276
-  // quotient estimate from the top 52 bits, at most 2 below floor(y / r)
-  const double top = (double)y[8] * 4294967296.0 + (double)y[7];
-  int32_t q = (int32_t)(top * FR_INV_RTOP1) - 1;
+  double t = 0.0, h = 0.0;
+#pragma unroll
+  for (int w = 0; w < 8; ++w) {
+    t = ((w & 1) ? Y[w >> 1] : X[w >> 1]) + h;
+    h = __builtin_floor(t * 2.3283064365386963e-10);  // exact floor(t / 2^32)
+    y[w] = (uint32_t)__builtin_fma(h, -4294967296.0, t);
+  }
+  y[8] = (uint32_t)h;
+  // quotient estimate from t = y[8] * 2^32 + y[7] (exact in fp64)
+  int32_t q = (int32_t)(t * FR_INV_RTOP1) - 1;
   q = q < 0 ? 0 : q;
-  // y -= q * r
   uint32_t carry = 0, br = 0;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
@@ -211,9 +212,10 @@ __device__ FRNTT_INLINE fr_t merge_reduce(const i32x16& a0, const i32x16& a1) {
     carry = (uint32_t)(p >> 32);
     y[i] = subb(y[i], (uint32_t)p, br, &br);
   }
-  y[8] = y[8] - carry - br;  // becomes 0
-  cond_sub_words(y, true);
-  cond_sub_words(y, false);
+  if (canonical) {
+    cond_sub_words(y, true);
+    cond_sub_words(y, false);
+  }
   fr_t o;
 #pragma unroll
   for (int i = 0; i < 8; ++i) o.w[i] = y[i];
@@ -240,16 +242,17 @@ struct LevelGeom {
 };
 
 // Route output digit k of vector v into the next level's row order (after
-// the inter-level twiddle w^(nn * k) of the size-2^(m + q_log)
+// the inter-level twiddle tw = w^(nn * k) of the size-2^(m + q_log)
 // sub-problem), or, after the last level, to row k of its line.
-__device__ FRNTT_INLINE void level_output(u32x4* lds, const PassParams& P, const DevTables& T,
-                                          const LevelGeom& g, int v, int k, fr_t y) {
+__device__ FRNTT_INLINE void level_output(u32x4* lds, const PassParams& P, const LevelGeom& g, int v, int k,
+                                          fr_t y, const fr_t& tw) {
   const int line = v & ((1 << P.log_g) - 1);
   const int rem = v >> P.log_g;
   const int kk = rem & ((1 << g.pprev_log) - 1);
   const int nn = rem >> g.pprev_log;
   if (!g.last) {
-    y = mont_mul(y, small_tw(T, P.dir, g.m + g.q_log, (uint32_t)(nn * k)));
+    // y may be any value below 2^256 here: it is the word-scanned operand
+    y = mont_mul(tw, y);
     const int nshift = g.q_log - g.next_m;
     const int n_next = nn >> nshift;
     const int nn2 = nn & ((1 << nshift) - 1);
@@ -260,27 +263,35 @@ __device__ FRNTT_INLINE void level_output(u32x4* lds, const PassParams& P, const
   }
 }
 
-// One MFMA level: every wave takes TPW tiles of 32 vectors. It first loads
-// the data fragments of all its tiles (lane l: bytes 16*(l/32)..+15 of
+// One MFMA level. Tiles of 32 vectors are spread over the 8 waves: each wave
+// takes TPW tiles, or, when there are fewer tiles than waves, KSPLIT waves
+// share a tile and each computes RHO / KSPLIT of its outputs. A wave first
+// loads the data fragments of its tiles (lane l: bytes 16*(l/32)..+15 of
 // vector l%32 for every input digit n), so that after the barrier the level
 // can overwrite LDS in place.
-template <int M, int TPW>
+template <int M, int TPW, int KSPLIT>
 __device__ FRNTT_INLINE void mfma_level(u32x4* lds, i32x4* lds_f, const PassParams& P, const DevTables& T,
                                         const LevelGeom& g) {
   constexpr int RHO = 1 << M;
+  constexpr int KCNT = RHO / KSPLIT;
   const int V = 1 << (P.log_t - M);
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int half = lane >> 5;
   const int col = lane & 31;
-  // stage this radix's constant blocks (RHO KiB) in LDS
+  const int tile0 = (wave / KSPLIT) * TPW;
+  const int kbase = (wave % KSPLIT) * KCNT;
+  // stage this radix's constant blocks (RHO KiB) and accumulator seeds
+  // (RHO x 2 x 16 int32) in LDS
   const i32x4* bat = T.bat[P.dir][M];
   for (int i = threadIdx.x; i < RHO * 64; i += kThreads) lds_f[i] = bat[i];
-  const i32x4* init = T.bat_init[P.dir][M];
+  const i32x4* init_g = T.bat_init[P.dir][M];
+  i32x4* init = lds_f + kBatMaxRho * 64;
+  for (int i = threadIdx.x; i < RHO * 8; i += kThreads) init[i] = init_g[i];
   i32x4 B[TPW][RHO];
 #pragma unroll
   for (int t = 0; t < TPW; ++t) {
-    const int v = (wave * TPW + t) * 32 + col;
+    const int v = (tile0 + t) * 32 + col;
 #pragma unroll
     for (int n = 0; n < RHO; ++n) {
       const u32x4 raw = lds[2 * (n * V + v) + half];
@@ -290,9 +301,17 @@ __device__ FRNTT_INLINE void mfma_level(u32x4* lds, i32x4* lds_f, const PassPara
   __syncthreads();
 #pragma unroll
   for (int t = 0; t < TPW; ++t) {
-    const int v = (wave * TPW + t) * 32 + col;
+    const int v = (tile0 + t) * 32 + col;
 #pragma unroll 1
-    for (int k0 = 0; k0 < RHO; k0 += 2) {
+    for (int k0 = kbase; k0 < kbase + KCNT; k0 += 2) {
+      const int k = k0 + half;  // this lane's output after the merge
+      // issue the inter-level twiddle load before the MFMA chain so its
+      // latency hides behind it
+      fr_t tw;
+      if (!g.last) {
+        const int nn = (v >> P.log_g) >> g.pprev_log;
+        tw = small_tw(T, P.dir, g.m + g.q_log, (uint32_t)(nn * k));
+      }
       i32x16 acc0 = load_init(init, k0, half);
       i32x16 acc1 = load_init(init, k0 + 1, half);
 #pragma unroll
@@ -302,8 +321,10 @@ __device__ FRNTT_INLINE void mfma_level(u32x4* lds, i32x4* lds_f, const PassPara
         acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, B[t][n], acc0, 0, 0, 0);
         acc1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, B[t][n], acc1, 0, 0, 0);
       }
-      const fr_t y = merge_reduce(acc0, acc1);
-      level_output(lds, P, T, g, v, k0 + half, y);
+      // outputs that get a twiddle product next may stay in [0, 3r)
+      const bool canonical = g.last && P.is_last;
+      const fr_t y = merge_reduce(acc0, acc1, canonical);
+      level_output(lds, P, g, v, k, y, tw);
     }
   }
   __syncthreads();
@@ -312,15 +333,16 @@ __device__ FRNTT_INLINE void mfma_level(u32x4* lds, i32x4* lds_f, const PassPara
 __device__ FRNTT_INLINE void run_mfma_level(u32x4* lds, i32x4* lds_f, const PassParams& P, const DevTables& T,
                                             const LevelGeom& g) {
   const int tiles = 1 << (P.log_t - g.m - 5);
-  const int tpw = tiles / kWaves;
-  switch (g.m * 16 + tpw) {
-    case 1 * 16 + 8: mfma_level<1, 8>(lds, lds_f, P, T, g); break;
-    case 1 * 16 + 4: mfma_level<1, 4>(lds, lds_f, P, T, g); break;
-    case 2 * 16 + 4: mfma_level<2, 4>(lds, lds_f, P, T, g); break;
-    case 2 * 16 + 2: mfma_level<2, 2>(lds, lds_f, P, T, g); break;
-    case 3 * 16 + 2: mfma_level<3, 2>(lds, lds_f, P, T, g); break;
-    case 3 * 16 + 1: mfma_level<3, 1>(lds, lds_f, P, T, g); break;
-    case 4 * 16 + 1: mfma_level<4, 1>(lds, lds_f, P, T, g); break;
+  const int tpw = tiles >= kWaves ? tiles / kWaves : 1;
+  const int ksplit = tiles >= kWaves ? 1 : kWaves / tiles;
+  switch (g.m * 256 + tpw * 16 + ksplit) {
+    case 1 * 256 + 8 * 16 + 1: mfma_level<1, 8, 1>(lds, lds_f, P, T, g); break;
+    case 1 * 256 + 4 * 16 + 1: mfma_level<1, 4, 1>(lds, lds_f, P, T, g); break;
+    case 2 * 256 + 4 * 16 + 1: mfma_level<2, 4, 1>(lds, lds_f, P, T, g); break;
+    case 2 * 256 + 2 * 16 + 1: mfma_level<2, 2, 1>(lds, lds_f, P, T, g); break;
+    case 3 * 256 + 2 * 16 + 1: mfma_level<3, 2, 1>(lds, lds_f, P, T, g); break;
+    case 3 * 256 + 1 * 16 + 1: mfma_level<3, 1, 1>(lds, lds_f, P, T, g); break;
+    case 4 * 256 + 1 * 16 + 1: mfma_level<4, 1, 1>(lds, lds_f, P, T, g); break;
     default: break;  // the host only builds supported level shapes
   }
 }

@@ -6,7 +6,7 @@ namespace frntt {
 
 __global__ __launch_bounds__(kThreads) void ntt_pass_mfma_kernel(PassParams P, DevTables T) {
   __shared__ u32x4 lds[2 << kMaxLogT];
-  __shared__ i32x4 lds_f[kBatMaxRho * 64];
+  __shared__ i32x4 lds_f[kBatMaxRho * 64 + kBatMaxRho * 8];
   run_pass<1>(lds, lds_f, P, T, logical_wg(P));
 }
 
