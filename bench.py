@@ -15,7 +15,6 @@ from __future__ import annotations
 import argparse
 import json
 import os
-import statistics
 import sys
 import time
 
@@ -32,19 +31,20 @@ def log(msg):
 
 
 def time_transform(ctx, torch, ptr, log_n, batch, kind, algo, steps, warmup, stream):
+    """Warm up, then time exactly `steps` back-to-back transforms between two
+    events on the launch stream, synchronised on both sides. Returns the
+    mean milliseconds per transform."""
     for _ in range(warmup):
         ctx.transform_checked(ptr, log_n, batch, kind, stream, algo)
     torch.cuda.synchronize()
-    times = []
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
     for _ in range(steps):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
         ctx.transform_checked(ptr, log_n, batch, kind, stream, algo)
-        e1.record()
-        e1.synchronize()
-        times.append(e0.elapsed_time(e1))
-    return times
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
 
 
 def cpu_baseline(log_n_sample=20, budget_s=20.0):
@@ -201,8 +201,7 @@ def main():
         log(f"timing 2^20 forward {name}")
         t = time_transform(ctx, torch, buf.data_ptr(), log_n, 1, fr.FWD, algo, args.steps, args.warmup,
                            stream)
-        res[name] = {"ms_median": statistics.median(t), "ms_mean": statistics.fmean(t),
-                     "melem_s": n / (statistics.median(t) * 1e-3) / 1e6, "plan": ctx.get_plan(algo, log_n)}
+        res[name] = {"ms": t, "melem_s": n / (t * 1e-3) / 1e6, "plan": ctx.get_plan(algo, log_n)}
     mf = res["mfma"]
     out["c2"] = res
 
@@ -217,8 +216,8 @@ def main():
             steps = max(3, args.steps // 5)
             t_f = time_transform(ctx, torch, b24.data_ptr(), 24, 1, fr.COSET, algo, steps, 2, stream)
             t_i = time_transform(ctx, torch, b24.data_ptr(), 24, 1, fr.COSET_INV, algo, steps, 2, stream)
-            c3[name] = {"coset_ms": statistics.median(t_f), "coset_inv_ms": statistics.median(t_i),
-                        "melem_s": n24 / (statistics.median(t_f) * 1e-3) / 1e6,
+            c3[name] = {"coset_ms": t_f, "coset_inv_ms": t_i, "melem_s": n24 / (t_f * 1e-3) / 1e6,
+                        "roundtrip_melem_s": n24 / ((t_f + t_i) * 1e-3) / 1e6,
                         "plan": ctx.get_plan(algo, 24)}
         out["c3"] = c3
         del b24
@@ -229,7 +228,7 @@ def main():
 
     # ---- roofline of the dominant kernel (the MFMA pass kernel): each of
     # the two launches of a 2^20 transform reads and writes every element once
-    per_launch_ms = mf["ms_median"] / len(mf["plan"])
+    per_launch_ms = mf["ms"] / len(mf["plan"])
     alg_bytes = 2 * n * 32
     achieved = alg_bytes / (per_launch_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -245,7 +244,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(mf["ms_median"], 5),
+        "ms_per_step": round(mf["ms"], 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

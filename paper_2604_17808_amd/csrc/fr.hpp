@@ -127,6 +127,40 @@ __device__ FRNTT_INLINE fr_t mont_mul(const fr_t& a, const fr_t& b) {
   return fr_reduce_once(o);
 }
 
+// 2r as eight 32-bit words.
+__host__ __device__ constexpr uint32_t two_r_word(int i) {
+  uint64_t c = 0;
+  uint32_t w = 0;
+  for (int j = 0; j <= i; ++j) {
+    uint64_t s = (uint64_t)fr_mod_word(j) * 2 + c;
+    w = (uint32_t)s;
+    c = s >> 32;
+  }
+  return w;
+}
+
+// y < 3r (eight words) -> y mod r: subtract 2r, then r, where no borrow
+__device__ FRNTT_INLINE void cond_sub_words(uint32_t* y, bool twice) {
+  uint32_t d[8], b = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) d[i] = subb(y[i], twice ? two_r_word(i) : fr_mod_word(i), b, &b);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) y[i] = b ? y[i] : d[i];
+}
+
+// y < 3r -> y mod r
+__device__ FRNTT_INLINE fr_t fr_reduce_3r(const fr_t& x) {
+  uint32_t y[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) y[i] = x.w[i];
+  cond_sub_words(y, true);
+  cond_sub_words(y, false);
+  fr_t o;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) o.w[i] = y[i];
+  return o;
+}
+
 __device__ FRNTT_INLINE fr_t fr_zero() {
   fr_t z;
 #pragma unroll

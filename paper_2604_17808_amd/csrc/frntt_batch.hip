@@ -158,7 +158,7 @@ int launch_batch(frntt_ctx* ctx, const BatchParams& P, size_t np, hipStream_t st
   if (e != hipSuccess) return set_hip_error(ctx, e);
   // one resident workgroup per CU (LDS bound); never more than there are items
   const int64_t grid = std::min<int64_t>(P.n_items, (int64_t)ctx->cu_count);
-  hipLaunchKernelGGL(ntt_batch_kernel, dim3((unsigned)grid), dim3(kThreads), 0, stream, P, ctx->tables);
+  hipLaunchKernelGGL(ntt_batch_kernel, dim3((unsigned)grid), dim3(kMfmaThreads), 0, stream, P, ctx->tables);
   return set_hip_error(ctx, hipGetLastError());
 }
 

@@ -33,23 +33,23 @@ struct DeviceGuard {
 // ------------------------------------------------------------------ plans
 
 // Split a pass radix 2^l into levels of at most 2^max_m, as even as possible.
+// Returns the level count; writes the levels only if they fit kMaxLevels.
 static int split_levels(int l, int max_m, int* out) {
   int n = (l + max_m - 1) / max_m;
   if (n < 1) n = 1;
+  if (n > kMaxLevels) return n;
   int base = l / n, extra = l % n;
   for (int i = 0; i < n; ++i) out[i] = base + (i < extra ? 1 : 0);
   return n;
 }
 
-// Can level m of a pass with 2^log_t staged elements run on MFMA? Every wave
-// takes the same number of 32-vector tiles, and tiles x radix <= 16 keeps a
-// wave's data fragments in 64 registers.
+// Can level m of a pass with 2^log_t staged elements run on MFMA? Each of
+// the 8 waves of a workgroup takes the same number TPW of 32-vector tiles,
+// and TPW * 2^m <= 16 keeps a wave's data fragments in 64 registers.
 bool mfma_level_ok(int m, int log_t) {
   if (m < 1 || m > 4) return false;
-  const int tiles_log = log_t - m - 5;
-  if (tiles_log < 3) return false;    // 8 waves, at least one tile each
-  const int tpw_log = tiles_log - 3;
-  return tpw_log + m <= 4;
+  const int tpw_log = log_t - m - 5 - 3;
+  return tpw_log >= 0 && tpw_log + m <= 4;
 }
 
 // Levels of pass p for the MFMA engine: radices of at most 16, as even as
@@ -58,16 +58,16 @@ bool mfma_level_ok(int m, int log_t) {
 static bool plan_levels(Plan& plan, int p, int log_t_pass) {
   const int l = plan.pass_log[p];
   int levs[kMaxLevels];
-  // fewest levels first (each costs a carry merge and a twiddle product)
-  const int max_m = 4;
-  int n = split_levels(l, max_m, levs);
-  bool ok = n <= kMaxLevels;
-  for (int i = 0; i < n; ++i) ok = ok && mfma_level_ok(levs[i], log_t_pass);
-  if (!ok && max_m == 5) {
-    n = split_levels(l, 4, levs);
+  // fewest levels first (each costs a carry merge and a twiddle product);
+  // smaller radices when the staged tile has too few vectors for 16
+  int n = 0;
+  bool ok = false;
+  for (int max_m = 4; max_m >= 1 && !ok; --max_m) {
+    n = split_levels(l, max_m, levs);
     ok = n <= kMaxLevels;
-    for (int i = 0; i < n; ++i) ok = ok && mfma_level_ok(levs[i], log_t_pass);
+    for (int i = 0; i < n && ok; ++i) ok = mfma_level_ok(levs[i], log_t_pass);
   }
+  if (!ok) n = 0;
   plan.nlev[p] = n;
   for (int i = 0; i < n; ++i) plan.lev_log[p][i] = levs[i];
   return ok;
@@ -225,11 +225,14 @@ int launch_passes(frntt_ctx* ctx, const std::vector<PassParams>& passes, int alg
   for (const PassParams& P : passes) {
     if (P.wg_count <= 0) continue;
     (void)algo;
-    if (P.engine == 1)
-      hipLaunchKernelGGL(ntt_pass_mfma_kernel, dim3((unsigned)P.wg_count), dim3(kThreads), 0, stream, P,
+    MfmaPassKernel plan_k = P.engine == 1 && P.log_t == kMaxLogT ? mfma_plan_kernel(P.nlev, P.lev_log) : nullptr;
+    if (plan_k)
+      hipLaunchKernelGGL(plan_k, dim3((unsigned)P.wg_count), dim3(kMfmaThreads), 0, stream, P, ctx->tables);
+    else if (P.engine == 1)
+      hipLaunchKernelGGL(ntt_pass_mfma_kernel, dim3((unsigned)P.wg_count), dim3(kMfmaThreads), 0, stream, P,
                          ctx->tables);
     else
-      hipLaunchKernelGGL(ntt_pass_bfly_kernel, dim3((unsigned)P.wg_count), dim3(kThreads), 0, stream, P,
+      hipLaunchKernelGGL(ntt_pass_bfly_kernel, dim3((unsigned)P.wg_count), dim3(kBflyThreads), 0, stream, P,
                          ctx->tables);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_hip_error(ctx, e);

@@ -14,6 +14,7 @@ namespace frntt {
 
 __global__ void ntt_pass_bfly_kernel(PassParams P, DevTables T);
 __global__ void ntt_pass_mfma_kernel(PassParams P, DevTables T);
+
 __global__ void ntt_batch_kernel(BatchParams B, DevTables T);
 __global__ void generate_kernel(u32x4* out, uint64_t seed, uint64_t stream_id, uint64_t start,
                                 uint64_t count);

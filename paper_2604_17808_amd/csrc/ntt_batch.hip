@@ -5,9 +5,9 @@
 
 namespace frntt {
 
-__global__ __launch_bounds__(kThreads) void ntt_batch_kernel(BatchParams B, DevTables T) {
+__global__ __launch_bounds__(kMfmaThreads) void ntt_batch_kernel(BatchParams B, DevTables T) {
   __shared__ u32x4 lds[2 << kMaxLogT];
-  __shared__ i32x4 lds_f[kBatMaxRho * 64 + kBatMaxRho * 8];
+  __shared__ i32x4 lds_f[bat_lds_size<4>()];
   // the item slot shares the constant-block area: it is written and read
   // only between passes, when no MFMA level uses that area
   int& item_sh = *reinterpret_cast<int*>(&lds_f[0]);
@@ -45,7 +45,7 @@ __global__ __launch_bounds__(kThreads) void ntt_batch_kernel(BatchParams B, DevT
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const PassParams& P = B.passes[p];
     const int64_t wg = B.item_wg[item];
-    run_pass<2>(lds, lds_f, P, T, wg);
+    run_pass<2, kMfmaThreads>(lds, lds_f, P, T, wg);
     __syncthreads();
     if (wave == 0) {
       __threadfence();

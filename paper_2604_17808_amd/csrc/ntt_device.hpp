@@ -12,8 +12,12 @@ typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 typedef int32_t i32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kMaxLogT = 12;           // elements staged per workgroup: 2^12 x 32 B = 128 KiB
-constexpr int kThreads = 512;          // 8 waves per workgroup
-constexpr int kWaves = kThreads / 64;
+// Threads per workgroup. The butterfly engine runs 16 waves (4 per SIMD, at
+// most 128 registers each); the MFMA engine runs 8 waves, whose 256-register
+// budget holds a level's data fragments and constant blocks together.
+constexpr int kBflyThreads = 1024;
+constexpr int kMfmaThreads = 512;
+constexpr int kMfmaWaves = kMfmaThreads / 64;
 constexpr int kMaxLevels = 6;
 constexpr int kMasterLog = 28;         // two-adicity of r
 constexpr int kSplit = 14;             // master twiddle exponent split 14 + 14 bits
@@ -66,6 +70,11 @@ struct BatchParams {
   unsigned int* done;         // per pass: finished workgroups (zeroed before launch)
   const int64_t* pass_wgs;    // workgroup count of each pass
 };
+
+// Specialised MFMA pass kernel for a 4096-element tile with these levels, or
+// nullptr (then the generic kernel runs).
+typedef void (*MfmaPassKernel)(PassParams, DevTables);
+MfmaPassKernel mfma_plan_kernel(int nlev, const int* lev);
 
 // ---- element access -------------------------------------------------------
 

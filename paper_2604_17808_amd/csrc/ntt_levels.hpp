@@ -16,9 +16,9 @@
 //     E[(k,h),(n,a)] (signed digit h of w^(kn) * 2^(8a) mod r) with the data
 //     bytes on int8 MFMA (Alg. 1's ByteDecompose and einsum), followed by the
 //     carry merge sum_h P_h 2^(8h) and reduction mod r (ByteMerge and the
-//     final correction), the inter-level twiddle, and a write into the row
-//     order the next level reads. The vector index is always the fastest
-//     LDS index.
+//     final correction), a write into the row order the next level reads,
+//     and then, as an elementwise phase over the tile, the inter-level
+//     twiddle. The vector index is always the fastest LDS index.
 // Both engines compute exact field values, so results are bit-identical.
 #pragma once
 #include "ntt_device.hpp"
@@ -48,6 +48,7 @@ __device__ FRNTT_INLINE void lds_st(u32x4* lds, int e, const fr_t& x) {
 
 // Stage the workgroup's G lines in LDS at position n * G + line (with the
 // coset pre-scale x_n * g^n in the first pass of a coset transform).
+template <int NT>
 __device__ FRNTT_INLINE void load_lines(u32x4* lds, const PassParams& P, const DevTables& T, int64_t wg) {
   const int T_el = 1 << P.log_t;
   const int G = 1 << P.log_g;
@@ -55,7 +56,7 @@ __device__ FRNTT_INLINE void load_lines(u32x4* lds, const PassParams& P, const D
   const int64_t nmask = (1ll << P.log_n) - 1;
   if (!P.is_last) {
     // pass axis strided: neighbouring threads take neighbouring lines
-    for (int e = tid; e < T_el; e += kThreads) {
+    for (int e = tid; e < T_el; e += NT) {
       const int n = e >> P.log_g, line = e & (G - 1);
       const LineMap mp = map_line(P, wg * G + line);
       const int64_t idx = mp.in_base + ((int64_t)n << mp.in_shift);
@@ -66,7 +67,7 @@ __device__ FRNTT_INLINE void load_lines(u32x4* lds, const PassParams& P, const D
   } else {
     // lines contiguous in memory: neighbouring threads take neighbouring n
     const int R = 1 << P.log_r;
-    for (int e = tid; e < T_el; e += kThreads) {
+    for (int e = tid; e < T_el; e += NT) {
       const int line = e >> P.log_r, n = e & (R - 1);
       const LineMap mp = map_line(P, wg * G + line);
       const int64_t idx = mp.in_base + n;
@@ -80,6 +81,7 @@ __device__ FRNTT_INLINE void load_lines(u32x4* lds, const PassParams& P, const D
 // Write output k of every line (found at LDS row k, or bitrev(k) after the
 // butterfly engine) to HBM, with the pass twiddle w^(rest * k) of the
 // size-2^(l+S) sub-problem, or the last pass's N^-1 / g^-k epilogue.
+template <int NT>
 __device__ FRNTT_INLINE void store_lines(const u32x4* lds, const PassParams& P, const DevTables& T, int64_t wg,
                                          bool bitrev) {
   const int T_el = 1 << P.log_t;
@@ -87,19 +89,22 @@ __device__ FRNTT_INLINE void store_lines(const u32x4* lds, const PassParams& P, 
   const int tid = threadIdx.x;
   // two elements in flight per thread: their table loads overlap
 #pragma unroll 2
-  for (int e = tid; e < T_el; e += kThreads) {
+  for (int e = tid; e < T_el; e += NT) {
     const int k = e >> P.log_g, line = e & (G - 1);
     const int row = bitrev ? (int)(__builtin_bitreverse32((uint32_t)k) >> (32 - P.log_r)) : k;
     fr_t y = lds_ld(lds, row * G + line);
     const LineMap mp = map_line(P, wg * G + line);
+    // y is below 3r after the MFMA engine (canonical after the butterfly):
+    // it is always the word-scanned operand of a product
     if (!P.is_last) {
-      // y may be below 2^256 but not reduced (MFMA engine): word-scanned operand
       y = mont_mul(pow_tw(T, P.dir, P.log_r + P.log_s, (uint64_t)mp.rest * (uint64_t)k), y);
     } else if (P.post == 1) {
-      y = mont_mul(y, ld_elem(T.ninv, P.log_n));
+      y = mont_mul(ld_elem(T.ninv, P.log_n), y);
     } else if (P.post == 2) {
       const uint32_t idx = (uint32_t)(mp.poly_off + ((int64_t)k << mp.out_shift));
-      y = mont_mul(y, mont_mul(ld_elem(T.ninv, P.log_n), coset_pow(T, 1, idx)));
+      y = mont_mul(mont_mul(ld_elem(T.ninv, P.log_n), coset_pow(T, 1, idx)), y);
+    } else if (!bitrev) {
+      y = fr_reduce_3r(y);
     }
     st_elem(P.dst, mp.out_base + ((int64_t)k << mp.out_shift), y);
   }
@@ -109,6 +114,7 @@ __device__ FRNTT_INLINE void store_lines(const u32x4* lds, const PassParams& P, 
 
 // log_r radix-2 DIF stages over every line, in place in LDS; afterwards row i
 // of a line holds output bitrev(i).
+template <int NT>
 __device__ FRNTT_INLINE void bfly_stages(u32x4* lds, const PassParams& P, const DevTables& T) {
   const int half_el = 1 << (P.log_t - 1);
   const int G = 1 << P.log_g;
@@ -118,7 +124,7 @@ __device__ FRNTT_INLINE void bfly_stages(u32x4* lds, const PassParams& P, const 
     const int log_span = P.log_r - 1 - s;
     const int span = 1 << log_span;
 #pragma unroll 1
-    for (int b = tid; b < half_el; b += kThreads) {
+    for (int b = tid; b < half_el; b += NT) {
       const int line = b & (G - 1);
       const int bb = b >> P.log_g;             // butterfly index inside the line
       const int j = bb & (span - 1);
@@ -136,27 +142,6 @@ __device__ FRNTT_INLINE void bfly_stages(u32x4* lds, const PassParams& P, const 
 
 // ------------------------------------------------------------ MFMA level
 
-// 2r as eight 32-bit words.
-__host__ __device__ constexpr uint32_t two_r_word(int i) {
-  uint64_t c = 0;
-  uint32_t w = 0;
-  for (int j = 0; j <= i; ++j) {
-    uint64_t s = (uint64_t)fr_mod_word(j) * 2 + c;
-    w = (uint32_t)s;
-    c = s >> 32;
-  }
-  return w;
-}
-
-// y (9 words, y < 3r after the quotient step) -> canonical
-__device__ FRNTT_INLINE void cond_sub_words(uint32_t* y, bool twice) {
-  uint32_t d[8], b = 0;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) d[i] = subb(y[i], twice ? two_r_word(i) : fr_mod_word(i), b, &b);
-#pragma unroll
-  for (int i = 0; i < 8; ++i) y[i] = b ? y[i] : d[i];
-}
-
 // Top 32-bit word of r plus one, inverted: floor(top / (r_top + 1)) never
 // exceeds the true quotient.
 #define FR_INV_RTOP1 (1.0 / 811880051.0)  // r_top = 0x30644e72 = 811880050
@@ -171,21 +156,27 @@ __device__ FRNTT_INLINE void cond_sub_words(uint32_t* y, bool twice) {
 // The merge runs on exact fp64 integers: a word group sum_j P_(4w+j) 2^(8j)
 // stays below 2^53, and splitting t into floor(t / 2^32) and the remainder
 // is exact. A quotient estimate from the top 52 bits, at most 2 below
-// floor(y / r), then brings y into [0, 3r); `canonical` finishes in [0, r).
-__device__ FRNTT_INLINE fr_t merge_reduce(const i32x16& a0, const i32x16& a1, bool canonical) {
+// floor(y / r), then brings y into [0, 3r).
+//
+// The work is cut into kMergeSteps steps of about ten vector instructions,
+// so that it can be spread over the MFMA issue slots of the next outputs.
+constexpr int kMergeSteps = 16;
+
+struct Merge {
+  i32x16 a0, a1;
   double w0[4], w1[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    w0[i] = __builtin_fma((double)a0[4 * i + 3], 16777216.0,
-             __builtin_fma((double)a0[4 * i + 2], 65536.0,
-              __builtin_fma((double)a0[4 * i + 1], 256.0, (double)a0[4 * i])));
-    w1[i] = __builtin_fma((double)a1[4 * i + 3], 16777216.0,
-             __builtin_fma((double)a1[4 * i + 2], 65536.0,
-              __builtin_fma((double)a1[4 * i + 1], 256.0, (double)a1[4 * i])));
-  }
   double X[4], Y[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  double t, h;
+  uint32_t y[9];
+  int32_t q;
+  uint32_t carry, br;
+
+  __device__ FRNTT_INLINE static double group(const i32x16& a, int i) {
+    return __builtin_fma((double)a[4 * i + 3], 16777216.0,
+            __builtin_fma((double)a[4 * i + 2], 65536.0,
+             __builtin_fma((double)a[4 * i + 1], 256.0, (double)a[4 * i])));
+  }
+  __device__ FRNTT_INLINE void swap(int i) {
     const uint64_t b0 = __builtin_bit_cast(uint64_t, w0[i]);
     const uint64_t b1 = __builtin_bit_cast(uint64_t, w1[i]);
     auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)b0, (uint32_t)b1, false, false);
@@ -193,34 +184,48 @@ __device__ FRNTT_INLINE fr_t merge_reduce(const i32x16& a0, const i32x16& a1, bo
     X[i] = __builtin_bit_cast(double, ((uint64_t)hi[0] << 32) | (uint32_t)lo[0]);  // word 2i
     Y[i] = __builtin_bit_cast(double, ((uint64_t)hi[1] << 32) | (uint32_t)lo[1]);  // word 2i + 1
   }
-  uint32_t y[9];
-  double t = 0.0, h = 0.0;
-#pragma unroll
-  for (int w = 0; w < 8; ++w) {
-    t = ((w & 1) ? Y[w >> 1] : X[w >> 1]) + h;
+  __device__ FRNTT_INLINE void carry_word(int w) {
+    t = ((w & 1) ? Y[w >> 1] : X[w >> 1]) + (w == 0 ? 0.0 : h);
     h = __builtin_floor(t * 2.3283064365386963e-10);  // exact floor(t / 2^32)
     y[w] = (uint32_t)__builtin_fma(h, -4294967296.0, t);
   }
-  y[8] = (uint32_t)h;
-  // quotient estimate from t = y[8] * 2^32 + y[7] (exact in fp64)
-  int32_t q = (int32_t)(t * FR_INV_RTOP1) - 1;
-  q = q < 0 ? 0 : q;
-  uint32_t carry = 0, br = 0;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
+  __device__ FRNTT_INLINE void sub_qr(int i) {
     const uint64_t p = (uint64_t)(uint32_t)q * fr_mod_word(i) + carry;
     carry = (uint32_t)(p >> 32);
     y[i] = subb(y[i], (uint32_t)p, br, &br);
   }
-  if (canonical) {
-    cond_sub_words(y, true);
-    cond_sub_words(y, false);
+  // step s of kMergeSteps (s is a constant after unrolling)
+  __device__ FRNTT_INLINE void step(int s) {
+    switch (s) {
+      case 0: case 1: case 2: case 3: w0[s] = group(a0, s); break;
+      case 4: case 5: case 6: case 7: w1[s - 4] = group(a1, s - 4); break;
+      case 8: swap(0); swap(1); break;
+      case 9: swap(2); swap(3); break;
+      case 10: carry_word(0); carry_word(1); break;
+      case 11: carry_word(2); carry_word(3); break;
+      case 12: carry_word(4); carry_word(5); break;
+      case 13:
+        carry_word(6); carry_word(7);
+        y[8] = (uint32_t)h;
+        break;
+      case 14:
+        // quotient estimate from t = y[8] * 2^32 + y[7] (exact in fp64)
+        q = (int32_t)(t * FR_INV_RTOP1) - 1;
+        q = q < 0 ? 0 : q;
+        carry = 0;
+        br = 0;
+        sub_qr(0); sub_qr(1); sub_qr(2); sub_qr(3);
+        break;
+      default: sub_qr(4); sub_qr(5); sub_qr(6); sub_qr(7); break;
+    }
   }
-  fr_t o;
+  __device__ FRNTT_INLINE fr_t result() const {
+    fr_t o;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) o.w[i] = y[i];
-  return o;
-}
+    for (int i = 0; i < 8; ++i) o.w[i] = y[i];
+    return o;
+  }
+};
 
 __device__ FRNTT_INLINE i32x16 load_init(const i32x4* init, int k, int half) {
   const i32x4* p = init + (k * 2 + half) * 4;
@@ -241,53 +246,121 @@ struct LevelGeom {
   int last;
 };
 
-// Route output digit k of vector v into the next level's row order (after
-// the inter-level twiddle tw = w^(nn * k) of the size-2^(m + q_log)
-// sub-problem), or, after the last level, to row k of its line.
-__device__ FRNTT_INLINE void level_output(u32x4* lds, const PassParams& P, const LevelGeom& g, int v, int k,
-                                          fr_t y, const fr_t& tw) {
+// LDS position of output digit k of vector v: the row order the next level
+// reads, or, after the last level, row k of its line.
+__device__ FRNTT_INLINE int level_out_pos(const PassParams& P, const LevelGeom& g, int v, int k) {
   const int line = v & ((1 << P.log_g) - 1);
   const int rem = v >> P.log_g;
   const int kk = rem & ((1 << g.pprev_log) - 1);
   const int nn = rem >> g.pprev_log;
-  if (!g.last) {
-    // y may be any value below 2^256 here: it is the word-scanned operand
-    y = mont_mul(tw, y);
-    const int nshift = g.q_log - g.next_m;
-    const int n_next = nn >> nshift;
-    const int nn2 = nn & ((1 << nshift) - 1);
-    const int col = line + ((kk + (k << g.pprev_log) + (nn2 << (g.pprev_log + g.m))) << P.log_g);
-    lds_st(lds, (n_next << (P.log_t - g.next_m)) + col, y);
-  } else {
-    lds_st(lds, ((kk + (k << g.pprev_log)) << P.log_g) + line, y);
+  if (g.last) return ((kk + (k << g.pprev_log)) << P.log_g) + line;
+  const int nshift = g.q_log - g.next_m;
+  const int n_next = nn >> nshift;
+  const int nn2 = nn & ((1 << nshift) - 1);
+  const int col = line + ((kk + (k << g.pprev_log) + (nn2 << (g.pprev_log + g.m))) << P.log_g);
+  return (n_next << (P.log_t - g.next_m)) + col;
+}
+
+// Inter-level twiddle, elementwise over the staged tile: the element at
+// next-level position e came from vector nn, digit k of this level and is
+// multiplied by w^(nn * k) of the size-2^(m + q_log) sub-problem. Inputs may
+// be any value below 2^256 (word-scanned operand); outputs are canonical.
+template <int NT>
+__device__ FRNTT_INLINE void level_twiddle(u32x4* lds, const PassParams& P, const DevTables& T,
+                                           const LevelGeom& g) {
+  const int T_el = 1 << P.log_t;
+  const int col_bits = P.log_t - g.next_m;
+  const int nshift = g.q_log - g.next_m;
+#pragma unroll 2
+  for (int e = threadIdx.x; e < T_el; e += NT) {
+    const int n_next = e >> col_bits;
+    const int c2 = (e & ((1 << col_bits) - 1)) >> P.log_g;
+    const int k = (c2 >> g.pprev_log) & ((1 << g.m) - 1);
+    const int nn = (n_next << nshift) + (c2 >> (g.pprev_log + g.m));
+    const fr_t tw = small_tw(T, P.dir, g.m + g.q_log, (uint32_t)(nn * k));
+    lds_st(lds, e, mont_mul(tw, lds_ld(lds, e)));
   }
 }
 
-// One MFMA level. Tiles of 32 vectors are spread over the 8 waves: each wave
-// takes TPW tiles, or, when there are fewer tiles than waves, KSPLIT waves
-// share a tile and each computes RHO / KSPLIT of its outputs. A wave first
-// loads the data fragments of its tiles (lane l: bytes 16*(l/32)..+15 of
-// vector l%32 for every input digit n), so that after the barrier the level
-// can overwrite LDS in place.
-template <int M, int TPW, int KSPLIT>
-__device__ FRNTT_INLINE void mfma_level(u32x4* lds, i32x4* lds_f, const PassParams& P, const DevTables& T,
-                                        const LevelGeom& g) {
+// Constant blocks of radix 2^M (RHO x 64 lanes x 16 B of signed digits)
+// followed by the accumulator seeds (RHO x 2 halves x 16 int32), staged in
+// LDS at dst.
+template <int M, int NT>
+__device__ FRNTT_INLINE void stage_bat(i32x4* dst, const DevTables& T, int dir) {
   constexpr int RHO = 1 << M;
-  constexpr int KCNT = RHO / KSPLIT;
+  const i32x4* bat = T.bat[dir][M];
+  const i32x4* seeds = T.bat_init[dir][M];
+  for (int i = threadIdx.x; i < RHO * 64; i += NT) dst[i] = bat[i];
+  for (int i = threadIdx.x; i < RHO * 8; i += NT) dst[RHO * 64 + i] = seeds[i];
+}
+
+template <int M>
+constexpr int bat_lds_size() { return (1 << M) * 72; }  // i32x4 units
+
+// One pipelined step of an MFMA level: issue the 2 x RHO MFMAs of the pair
+// (k0, k0 + 1) of one tile into (n0, n1), seeded with the signed-digit
+// correction and the positive bias, while the merge `mg` of the previous pair
+// (if `merging`) advances by kMergeSteps / RHO steps per input digit. The
+// constant blocks are loaded one digit ahead, and a scheduling barrier after
+// each digit keeps the vector work between the MFMAs, so the matrix and
+// vector pipes of a SIMD overlap within the wave.
+template <int RHO>
+__device__ FRNTT_INLINE void mfma_pair_merge(const i32x4* lds_f, const i32x4* init, const i32x4 (&Bt)[RHO],
+                                             int k0, int lane, int half, i32x16& n0, i32x16& n1, Merge& mg,
+                                             bool merging) {
+  constexpr int SPN = kMergeSteps / RHO;  // merge steps per input digit
+  n0 = load_init(init, k0, half);
+  n1 = load_init(init, k0 + 1, half);
+  i32x4 a0 = lds_f[lane];  // k * 0 = 0
+  i32x4 a1 = a0;
+#pragma unroll
+  for (int n = 0; n < RHO; ++n) {
+    i32x4 p0 = a0, p1 = a1;
+    if (n + 1 < RHO) {
+      p0 = lds_f[((k0 * (n + 1)) & (RHO - 1)) * 64 + lane];
+      p1 = lds_f[(((k0 + 1) * (n + 1)) & (RHO - 1)) * 64 + lane];
+    }
+    n0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, Bt[n], n0, 0, 0, 0);
+    if (merging) {
+#pragma unroll
+      for (int s = 0; s < (SPN + 1) / 2; ++s) mg.step(n * SPN + s);
+    }
+    n1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, Bt[n], n1, 0, 0, 0);
+    if (merging) {
+#pragma unroll
+      for (int s = (SPN + 1) / 2; s < SPN; ++s) mg.step(n * SPN + s);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    a0 = p0;
+    a1 = p1;
+  }
+}
+
+// One MFMA level. The 2^(log_t - m) vectors form tiles of 32; each of the 8
+// waves takes TPW whole tiles. A wave first loads the data fragments of its
+// tiles (lane l: bytes 16*(l/32)..+15 of vector l%32 for every input digit
+// n), so that after the barrier the level can overwrite LDS in place. The
+// output pairs of a wave form a software pipeline: the MFMAs of pair i + 1
+// run while pair i is merged, reduced below 3r and written (untwiddled) to
+// the position the next level reads. The inter-level twiddle follows as its
+// own elementwise phase.
+template <int M, int TPW>
+__device__ FRNTT_INLINE void mfma_level(u32x4* lds, i32x4* blk, const PassParams& P, const DevTables& T,
+                                        const LevelGeom& g, bool stage) {
+  constexpr int RHO = 1 << M;
+  constexpr int NKP = RHO / 2;  // output pairs per tile
+  static_assert(kMergeSteps % RHO == 0, "merge steps spread evenly over the digits");
   const int V = 1 << (P.log_t - M);
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int half = lane >> 5;
   const int col = lane & 31;
-  const int tile0 = (wave / KSPLIT) * TPW;
-  const int kbase = (wave % KSPLIT) * KCNT;
-  // stage this radix's constant blocks (RHO KiB) and accumulator seeds
-  // (RHO x 2 x 16 int32) in LDS
-  const i32x4* bat = T.bat[P.dir][M];
-  for (int i = threadIdx.x; i < RHO * 64; i += kThreads) lds_f[i] = bat[i];
-  const i32x4* init_g = T.bat_init[P.dir][M];
-  i32x4* init = lds_f + kBatMaxRho * 64;
-  for (int i = threadIdx.x; i < RHO * 8; i += kThreads) init[i] = init_g[i];
+  const int tile0 = wave * TPW;
+  // this radix's constant blocks and accumulator seeds (staged here, or for
+  // the whole pass before its loads)
+  if (stage) stage_bat<M, kMfmaThreads>(blk, T, P.dir);
+  const i32x4* lds_f = blk;
+  const i32x4* init = blk + RHO * 64;
   i32x4 B[TPW][RHO];
 #pragma unroll
   for (int t = 0; t < TPW; ++t) {
@@ -299,50 +372,53 @@ __device__ FRNTT_INLINE void mfma_level(u32x4* lds, i32x4* lds_f, const PassPara
     }
   }
   __syncthreads();
+  Merge mg;
+  i32x16 n0, n1;
+  mfma_pair_merge<RHO>(lds_f, init, B[0], 0, lane, half, n0, n1, mg, false);
 #pragma unroll
   for (int t = 0; t < TPW; ++t) {
     const int v = (tile0 + t) * 32 + col;
 #pragma unroll 1
-    for (int k0 = kbase; k0 < kbase + KCNT; k0 += 2) {
-      const int k = k0 + half;  // this lane's output after the merge
-      // issue the inter-level twiddle load before the MFMA chain so its
-      // latency hides behind it
-      fr_t tw;
-      if (!g.last) {
-        const int nn = (v >> P.log_g) >> g.pprev_log;
-        tw = small_tw(T, P.dir, g.m + g.q_log, (uint32_t)(nn * k));
-      }
-      i32x16 acc0 = load_init(init, k0, half);
-      i32x16 acc1 = load_init(init, k0 + 1, half);
+    for (int kp = 0; kp < NKP; ++kp) {
+      mg.a0 = n0;
+      mg.a1 = n1;
+      const bool more = kp + 1 < NKP || t + 1 < TPW;
+      if (more) {
+        const int tn = kp + 1 < NKP ? t : t + 1;
+        const int kn = kp + 1 < NKP ? 2 * kp + 2 : 0;
+        if (tn == t) mfma_pair_merge<RHO>(lds_f, init, B[t], kn, lane, half, n0, n1, mg, true);
+        else mfma_pair_merge<RHO>(lds_f, init, B[t + 1 < TPW ? t + 1 : t], kn, lane, half, n0, n1, mg, true);
+      } else {
 #pragma unroll
-      for (int n = 0; n < RHO; ++n) {
-        const i32x4 a0 = lds_f[((k0 * n) & (RHO - 1)) * 64 + lane];
-        const i32x4 a1 = lds_f[(((k0 + 1) * n) & (RHO - 1)) * 64 + lane];
-        acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, B[t][n], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, B[t][n], acc1, 0, 0, 0);
+        for (int st = 0; st < kMergeSteps; ++st) mg.step(st);
       }
-      // outputs that get a twiddle product next may stay in [0, 3r)
-      const bool canonical = g.last && P.is_last;
-      const fr_t y = merge_reduce(acc0, acc1, canonical);
-      level_output(lds, P, g, v, k, y, tw);
+      lds_st(lds, level_out_pos(P, g, v, 2 * kp + half), mg.result());
     }
   }
   __syncthreads();
+  if (!g.last) {
+    level_twiddle<kMfmaThreads>(lds, P, T, g);
+    __syncthreads();
+  }
 }
 
+// Level shapes: 2^(log_t - m - 5) tiles of 32 vectors, TPW = tiles / 8 per
+// wave (the host admits only levels with at least 8 tiles and TPW * RHO <= 16,
+// so a wave's data fragments take at most 64 registers).
 __device__ FRNTT_INLINE void run_mfma_level(u32x4* lds, i32x4* lds_f, const PassParams& P, const DevTables& T,
                                             const LevelGeom& g) {
-  const int tiles = 1 << (P.log_t - g.m - 5);
-  const int tpw = tiles >= kWaves ? tiles / kWaves : 1;
-  const int ksplit = tiles >= kWaves ? 1 : kWaves / tiles;
-  switch (g.m * 256 + tpw * 16 + ksplit) {
-    case 1 * 256 + 8 * 16 + 1: mfma_level<1, 8, 1>(lds, lds_f, P, T, g); break;
-    case 1 * 256 + 4 * 16 + 1: mfma_level<1, 4, 1>(lds, lds_f, P, T, g); break;
-    case 2 * 256 + 4 * 16 + 1: mfma_level<2, 4, 1>(lds, lds_f, P, T, g); break;
-    case 2 * 256 + 2 * 16 + 1: mfma_level<2, 2, 1>(lds, lds_f, P, T, g); break;
-    case 3 * 256 + 2 * 16 + 1: mfma_level<3, 2, 1>(lds, lds_f, P, T, g); break;
-    case 3 * 256 + 1 * 16 + 1: mfma_level<3, 1, 1>(lds, lds_f, P, T, g); break;
-    case 4 * 256 + 1 * 16 + 1: mfma_level<4, 1, 1>(lds, lds_f, P, T, g); break;
+  const int tpw = 1 << (P.log_t - g.m - 5 - 3);
+  switch (g.m * 16 + tpw) {
+    case 1 * 16 + 8: mfma_level<1, 8>(lds, lds_f, P, T, g, true); break;
+    case 1 * 16 + 4: mfma_level<1, 4>(lds, lds_f, P, T, g, true); break;
+    case 1 * 16 + 2: mfma_level<1, 2>(lds, lds_f, P, T, g, true); break;
+    case 1 * 16 + 1: mfma_level<1, 1>(lds, lds_f, P, T, g, true); break;
+    case 2 * 16 + 4: mfma_level<2, 4>(lds, lds_f, P, T, g, true); break;
+    case 2 * 16 + 2: mfma_level<2, 2>(lds, lds_f, P, T, g, true); break;
+    case 2 * 16 + 1: mfma_level<2, 1>(lds, lds_f, P, T, g, true); break;
+    case 3 * 16 + 2: mfma_level<3, 2>(lds, lds_f, P, T, g, true); break;
+    case 3 * 16 + 1: mfma_level<3, 1>(lds, lds_f, P, T, g, true); break;
+    case 4 * 16 + 1: mfma_level<4, 1>(lds, lds_f, P, T, g, true); break;
     default: break;  // the host only builds supported level shapes
   }
 }
@@ -365,16 +441,61 @@ __device__ FRNTT_INLINE void mfma_levels(u32x4* lds, i32x4* lds_f, const PassPar
 
 // ------------------------------------------------------------- one pass
 
+// A pass whose levels are known at compile time (radices 2^M0, 2^M1 and,
+// if M2 > 0, 2^M2, staged tile of 4096 elements): the constant blocks of
+// its (at most two) distinct radices are staged once, together with the
+// tile's HBM loads, and every level shape is fixed.
+template <int M0, int M1, int M2>
+struct PassPlan {
+  static constexpr int kLevels = M2 > 0 ? 3 : 2;
+  static_assert(M1 == M0 || M2 == 0 || M2 == M0 || M2 == M1, "at most two distinct radices");
+  static constexpr int kOff1 = M1 == M0 ? 0 : bat_lds_size<M0>();
+  static constexpr int kOff2 = M2 == M0 ? 0 : kOff1;
+  static constexpr int kLds = bat_lds_size<M0>() + (M1 == M0 ? 0 : bat_lds_size<M1>()) +
+                              (M2 > 0 && M2 != M0 && M2 != M1 ? bat_lds_size<M2>() : 0);
+};
+constexpr int kPlanBatLds = bat_lds_size<4>() + bat_lds_size<3>();
+
+__device__ FRNTT_INLINE LevelGeom level_geom(int m, int pprev, int q, int next_m) {
+  LevelGeom g;
+  g.m = m;
+  g.pprev_log = pprev;
+  g.q_log = q;
+  g.next_m = next_m;
+  g.last = next_m == 0;
+  return g;
+}
+
+template <int M0, int M1, int M2>
+__device__ FRNTT_INLINE void run_pass_plan(u32x4* lds, i32x4* lds_f, const PassParams& P, const DevTables& T,
+                                           int64_t wg) {
+  using PL = PassPlan<M0, M1, M2>;
+  constexpr int LT = kMaxLogT;  // staged elements 2^12
+  stage_bat<M0, kMfmaThreads>(lds_f, T, P.dir);
+  if (M1 != M0) stage_bat<M1, kMfmaThreads>(lds_f + PL::kOff1, T, P.dir);
+  load_lines<kMfmaThreads>(lds, P, T, wg);
+  __syncthreads();
+  mfma_level<M0, (1 << (LT - M0 - 8))>(lds, lds_f, P, T, level_geom(M0, 0, M1 + M2, M1), false);
+  mfma_level<M1, (1 << (LT - M1 - 8))>(lds, lds_f + PL::kOff1, P, T, level_geom(M1, M0, M2, M2), false);
+  if (M2 > 0) {
+    constexpr int M2c = M2 > 0 ? M2 : 1;
+    mfma_level<M2c, (1 << (LT - M2c - 8))>(lds, lds_f + PL::kOff2, P, T, level_geom(M2, M0 + M1, 0, 0), false);
+  }
+  store_lines<kMfmaThreads>(lds, P, T, wg, false);
+}
+
 // ENGINE: 0 butterfly only, 1 MFMA only, 2 per-pass choice (P.engine).
-template <int ENGINE>
+// NT: threads per workgroup (the MFMA engine runs with kMfmaThreads).
+template <int ENGINE, int NT>
 __device__ FRNTT_INLINE void run_pass(u32x4* lds, i32x4* lds_f, const PassParams& P, const DevTables& T,
                                       int64_t wg) {
-  load_lines(lds, P, T, wg);
+  static_assert(ENGINE == 0 || NT == kMfmaThreads, "MFMA levels assume kMfmaThreads");
+  load_lines<NT>(lds, P, T, wg);
   __syncthreads();
   const bool use_mfma = ENGINE == 1 || (ENGINE == 2 && P.engine == 1);
   if (use_mfma) mfma_levels(lds, lds_f, P, T);
-  else bfly_stages(lds, P, T);
-  store_lines(lds, P, T, wg, !use_mfma);
+  else bfly_stages<NT>(lds, P, T);
+  store_lines<NT>(lds, P, T, wg, !use_mfma);
 }
 
 }  // namespace frntt

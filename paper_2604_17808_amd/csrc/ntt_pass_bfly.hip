@@ -3,9 +3,9 @@
 
 namespace frntt {
 
-__global__ __launch_bounds__(kThreads) void ntt_pass_bfly_kernel(PassParams P, DevTables T) {
+__global__ __launch_bounds__(kBflyThreads) void ntt_pass_bfly_kernel(PassParams P, DevTables T) {
   __shared__ u32x4 lds[2 << kMaxLogT];
-  run_pass<0>(lds, nullptr, P, T, logical_wg(P));
+  run_pass<0, kBflyThreads>(lds, nullptr, P, T, logical_wg(P));
 }
 
 }  // namespace frntt
