@@ -24,6 +24,13 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 INT8_PEAK_TOPS = 5000.0        # MI355X dense int8 MFMA, TOP/s
+# 32x32+64-bit integer multiply-adds: 256 CUs x 64 lanes x 2.4 GHz, one per
+# lane per clock (the lane rate of the 78.6 TFLOP/s fp64 vector peak)
+MAD_PEAK_TMADS = 256 * 64 * 2.4e9 / 1e12
+MADS_PER_PRODUCT = 162         # Montgomery product on nine 29-bit limbs (9 rows x 18)
+MADS_PER_MERGE = 20            # carry merge: 12 for the word groups + 8 for the quotient step
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_mfma_fwd_2e20.txt")
+KERNEL_SOURCES = ["fr.hpp", "ntt_device.hpp", "ntt_levels.hpp", "ntt_pass_mfma.hip"]
 
 
 def log(msg):
@@ -45,6 +52,61 @@ def time_transform(ctx, torch, ptr, log_n, batch, kind, algo, steps, warmup, str
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps
+
+
+def level_split(l, max_m=4):
+    """Radices (log2) of the MFMA levels of a pass of radix 2^l with a
+    4096-element tile: fewest levels of at most 2^max_m, as even as possible
+    (the library's default split)."""
+    n = max(1, -(-l // max_m))
+    base, extra = divmod(l, n)
+    return [base + (1 if i < extra else 0) for i in range(n)]
+
+
+def algorithmic_work(plan, kind=0):
+    """Per-element multiply-adds and int8 MFMA operations of each pass of a
+    transform (forward: kind 0) with HBM passes `plan`."""
+    out = []
+    for p, l in enumerate(plan):
+        levs = level_split(l)
+        mads = MADS_PER_MERGE * len(levs) + MADS_PER_PRODUCT * (len(levs) - 1)
+        if p + 1 < len(plan):
+            mads += 2 * MADS_PER_PRODUCT          # pass twiddle: table product + apply
+        if p == 0 and kind == 2:
+            mads += 2 * MADS_PER_PRODUCT          # coset pre-scale
+        if p + 1 == len(plan) and kind == 1:
+            mads += MADS_PER_PRODUCT              # N^-1
+        if p + 1 == len(plan) and kind == 3:
+            mads += 3 * MADS_PER_PRODUCT          # N^-1 g^-k
+        out.append({"levels": levs, "mads": mads, "mfma_ops": 2048 * sum(1 << m for m in levs)})
+    return out
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2604_17808_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the MFMA pass kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None if the kernel sources
+    changed since the counters were taken."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("source_sha256") != kernel_source_hash():
+            return None
+        return float(kv["bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(log_n_sample=20, budget_s=20.0):
@@ -164,11 +226,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing on host cores")
     ap.add_argument("--quick", action="store_true", help="headline config only")
+    ap.add_argument("--only", default="c3,c4,c5",
+                    help="comma list of the other configurations to run (c3, c4, c5)")
     ap.add_argument("--c4-replays", type=int, default=200)
     ap.add_argument("--calib", action="store_true",
                     help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
     ap.add_argument("--serve-requests", type=int, default=10000)
     args = ap.parse_args()
+    extra = set() if args.quick else {c.strip() for c in args.only.split(",") if c.strip()}
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
@@ -205,8 +270,8 @@ def main():
     mf = res["mfma"]
     out["c2"] = res
 
-    if not args.quick:
-        # ---- 2^24 coset NTT then coset INTT (MFMA form), per transform
+    if "c3" in extra:
+        # ---- 2^24 coset NTT then coset INTT, both forms, per transform
         log(f"timing 2^24 coset round trip")
         n24 = 1 << 24
         b24 = torch.empty((n24, 4), dtype=torch.int64, device="cuda:0")
@@ -222,18 +287,29 @@ def main():
         out["c3"] = c3
         del b24
 
-    if not args.quick:
+    if "c4" in extra:
         out["c4"] = bench_c4(ctx, torch, fr, stream, args.c4_replays)
+    if "c5" in extra:
         out["c5"] = bench_c5(ctx, fr, args.serve_requests)
 
-    # ---- roofline of the dominant kernel (the MFMA pass kernel): each of
-    # the two launches of a 2^20 transform reads and writes every element once
-    per_launch_ms = mf["ms"] / len(mf["plan"])
-    alg_bytes = 2 * n * 32
-    achieved = alg_bytes / (per_launch_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "ntt_pass_mfma_kernel", "launch_ms": round(per_launch_ms, 5)}
+    # ---- roofline of the dominant kernel (the MFMA pass kernel) on the
+    # headline workload: algorithmic work per launch / average launch time
+    work = algorithmic_work(mf["plan"])
+    launches = len(mf["plan"])
+    per_launch_ms = mf["ms"] / launches
+    t = per_launch_ms * 1e-3
+    mads = n * sum(w["mads"] for w in work) / launches
+    ops = n * sum(w["mfma_ops"] for w in work) / launches
+    hbm = 2 * n * 32
+    achieved = mads / t / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(MAD_PEAK_TMADS, 2),
+                "unit": "Tmad/s", "frac": round(achieved / MAD_PEAK_TMADS, 4), "traffic": measured_traffic(),
+                "kernel": "ntt_pass_mfma_plan_kernel", "launch_ms": round(per_launch_ms, 5),
+                "mads_per_launch": mads,
+                "hbm": {"achieved_gbs": round(hbm / t / 1e9, 1), "peak_gbs": HBM_PEAK_GBS,
+                        "frac": round(hbm / t / 1e9 / HBM_PEAK_GBS, 4), "bytes_per_launch": hbm},
+                "mfma_int8": {"achieved_tops": round(ops / t / 1e12, 1), "peak_tops": INT8_PEAK_TOPS,
+                              "frac": round(ops / t / 1e12 / INT8_PEAK_TOPS, 4), "ops_per_launch": ops}}
 
     cpu = None if args.no_cpu else cpu_baseline()
 

@@ -2,13 +2,11 @@
 //
 // An element of the BN254 scalar field is held as eight 32-bit little-endian
 // words (the paper's "D 32-bit digits", Related Work: Arithmetic
-// Implementations). Products use Montgomery multiplication with R = 2^256
-// (the paper's "radix Mont" baseline), in the coarsely integrated operand
-// scanning form with the carry-free inner step of Botrel and El Housni
-// ("Faster big-integer modular multiplication for most moduli", 2020), which
-// applies because the top word of r is below 2^31 - 1. Twiddle constants are
-// kept in Montgomery form w*R mod r, so mont_mul(x, w*R) = x*w mod r maps
-// canonical inputs to canonical outputs without domain conversions.
+// Implementations). Products use Montgomery multiplication (the paper's
+// "radix Mont" baseline) in a reduced-radix form: nine 29-bit limbs with
+// lazy carries, R = 2^261 (see mont_mul). Twiddle constants are kept in
+// Montgomery form w*R mod r, so mont_mul(x, w*R) = x*w mod r maps canonical
+// inputs to canonical outputs without domain conversions.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -30,7 +28,6 @@ struct fr_t {
 #define FR_R5 0xb85045b6u
 #define FR_R6 0xe131a029u
 #define FR_R7 0x30644e72u
-#define FR_NPRIME 0xefffffffu  // -r^-1 mod 2^32
 
 __host__ __device__ constexpr uint32_t fr_mod_word(int i) {
   return i == 0 ? FR_R0 : i == 1 ? FR_R1 : i == 2 ? FR_R2 : i == 3 ? FR_R3
@@ -86,45 +83,99 @@ __device__ FRNTT_INLINE fr_t fr_sub(const fr_t& a, const fr_t& b) {
   return o;
 }
 
-// x + y as a 64-bit value (carry in the high word). Written with an explicit
-// add-with-carry so the pair feeds v_mad_u64_u32 directly, without
-// zero-extension moves.
-__device__ FRNTT_INLINE uint64_t add_2x32(uint32_t x, uint32_t y) {
-  uint32_t carry;
-  const uint32_t lo = __builtin_addc(x, y, 0u, &carry);
-  return ((uint64_t)carry << 32) | lo;
+// ---- Montgomery product on 29-bit limbs -----------------------------------
+//
+// The product runs on nine 29-bit limbs (261 bits) with 64-bit column
+// accumulators: every partial product is below 2^58 and a column collects at
+// most 18 of them (a*b and m*r, each limb position once per row of the
+// operand scan) plus a carry below 2^36, so it stays below 2^63 and every
+// multiply-add is a single 32x32+64-bit instruction with no carry handling
+// inside the rows. The Montgomery radix is R = 2^261; -r^-1 mod 2^29 is
+// 2^28 - 1 because r = 1 + 2^28 (mod 2^29).
+constexpr uint32_t kLimbMask = (1u << 29) - 1;
+constexpr uint32_t kNprime29 = 0x0fffffffu;
+
+__host__ __device__ constexpr uint32_t fr_limb29(int k) {
+  return k == 0 ? 0x10000001u : k == 1 ? 0x1f0fac9fu : k == 2 ? 0x0e5c2450u : k == 3 ? 0x07d090f3u
+       : k == 4 ? 0x1585d283u : k == 5 ? 0x02db40c0u : k == 6 ? 0x00a6e141u : k == 7 ? 0x0e5c2634u
+       : 0x0030644eu;
 }
 
-// Montgomery product a*b*2^-256 mod r for a, b < r; result canonical.
-// Row i adds a*b_i and m*r with m chosen to clear the low word, then shifts
-// one word; the two carry chains of a row are interleaved (A for a*b_i, C
-// for m*r), each step one 32x32+64 multiply-add.
-__device__ FRNTT_INLINE fr_t mont_mul(const fr_t& a, const fr_t& b) {
-  uint32_t t[8];
+// eight 32-bit words -> nine 29-bit limbs (funnel shifts on registers)
+__device__ FRNTT_INLINE void to_limbs29(const fr_t& x, uint32_t* l) {
 #pragma unroll
-  for (int j = 0; j < 8; ++j) t[j] = 0;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    uint64_t p = (uint64_t)a.w[0] * b.w[i] + t[0];
-    uint32_t A = (uint32_t)(p >> 32);
-    const uint32_t t0 = (uint32_t)p;
-    const uint32_t m = t0 * FR_NPRIME;
-    uint64_t q = (uint64_t)m * FR_R0 + t0;
-    uint32_t C = (uint32_t)(q >> 32);
-#pragma unroll
-    for (int j = 1; j < 8; ++j) {
-      p = (uint64_t)a.w[j] * b.w[i] + add_2x32(t[j], A);
-      A = (uint32_t)(p >> 32);
-      q = (uint64_t)m * fr_mod_word(j) + add_2x32((uint32_t)p, C);
-      C = (uint32_t)(q >> 32);
-      t[j - 1] = (uint32_t)q;
-    }
-    t[7] = C + A;
+  for (int k = 0; k < 9; ++k) {
+    const int bit = 29 * k, wi = bit >> 5, sh = bit & 31;
+    uint32_t v;
+    if (sh + 29 <= 32 || wi + 1 >= 8) v = x.w[wi] >> sh;
+    else v = __builtin_amdgcn_alignbit(x.w[wi + 1], x.w[wi], (uint32_t)sh);
+    l[k] = v & kLimbMask;
   }
-  fr_t o;
+}
+
+// Montgomery product a*b*2^-261 mod r for any a, b < 2^256; canonical
+// result. Row i adds a*b_i and m*r (m clears the low limb), then drops one
+// limb; the result is below 2r before the final subtraction. The work is
+// split into load(), nine row()s and finish(), so that it can also be spread
+// over the MFMA issue slots of the matrix form.
+struct MontMul {
+  uint32_t al[9], bl[9];
+  uint64_t t[9];
+
+  __device__ FRNTT_INLINE void load(const fr_t& a, const fr_t& b) {
+    to_limbs29(a, al);
+    to_limbs29(b, bl);
+  }
+  __device__ FRNTT_INLINE void row(int i) {
+    if (i == 0) {
 #pragma unroll
-  for (int j = 0; j < 8; ++j) o.w[j] = t[j];
-  return fr_reduce_once(o);
+      for (int j = 0; j < 9; ++j) t[j] = (uint64_t)al[j] * bl[0];
+    } else {
+#pragma unroll
+      for (int j = 0; j < 9; ++j) t[j] += (uint64_t)al[j] * bl[i];
+    }
+    const uint32_t m = ((uint32_t)t[0] * kNprime29) & kLimbMask;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) t[j] += (uint64_t)m * fr_limb29(j);
+    const uint64_t c = t[0] >> 29;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) t[j] = t[j + 1];
+    t[8] = 0;
+    t[0] += c;
+  }
+  __device__ FRNTT_INLINE fr_t finish() const {
+    // carry-propagate the columns into 29-bit limbs, then pack 32-bit words
+    uint32_t l[9];
+    uint64_t c = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint64_t v = t[j] + c;
+      l[j] = (uint32_t)v & kLimbMask;
+      c = v >> 29;
+    }
+    l[8] = (uint32_t)(t[8] + c);
+    // word i = bits [32 i, 32 i + 32): limb k from bit sh on, then the next
+    // one or two limbs (32-bit shifts; the limbs are below 2^29)
+    fr_t o;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int bit = 32 * i, k = bit / 29, sh = bit % 29;
+      uint32_t v = l[k] >> sh;
+      const int have = 29 - sh;
+      if (k + 1 < 9) v |= l[k + 1] << have;
+      if (have + 29 < 32 && k + 2 < 9) v |= l[k + 2] << (have + 29);
+      o.w[i] = v;
+    }
+    return fr_reduce_once(o);
+  }
+};
+
+__device__ FRNTT_INLINE fr_t mont_mul(const fr_t& a, const fr_t& b) {
+  MontMul mm;
+  mm.load(a, b);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) mm.row(i);
+  return mm.finish();
 }
 
 // 2r as eight 32-bit words.

@@ -23,7 +23,7 @@ constexpr int kMasterLog = 28;         // two-adicity of r
 constexpr int kSplit = 14;             // master twiddle exponent split 14 + 14 bits
 
 // Device constant tables built at context creation. Field elements are 32 B
-// (two u32x4); "mont" marks Montgomery form (value * 2^256 mod r).
+// (two u32x4); "mont" marks Montgomery form (value * 2^261 mod r).
 struct DevTables {
   const u32x4* tw_lo[2];      // [dir] mont w28^(+-j), j < 2^14            (w28 = w_{2^28})
   const u32x4* tw_hi[2];      // [dir] mont w28^(+-(2^14 j)), j < 2^14
@@ -33,6 +33,10 @@ struct DevTables {
   const u32x4* ninv;          // mont 2^-L for L = 0..28
   const i32x4* bat[2][6];     // [dir][log rho] rho blocks x 64 lanes x 16 B of signed digits
   const i32x4* bat_init[2][6];// [dir][log rho] rho x 2 halves x 16 int32 accumulator seeds
+  // 2^8, 2^16, 2^24: the byte-plane weights of the carry merge, passed as
+  // kernel arguments so that the word sums stay 32x32+64-bit multiply-adds
+  // (which overlap with MFMA) instead of becoming 64-bit shift-adds
+  uint32_t byte_w[3];
 };
 
 // One HBM pass of the multi-pass transform.

@@ -142,81 +142,82 @@ __device__ FRNTT_INLINE void bfly_stages(u32x4* lds, const PassParams& P, const 
 
 // ------------------------------------------------------------ MFMA level
 
-// Top 32-bit word of r plus one, inverted: floor(top / (r_top + 1)) never
-// exceeds the true quotient.
+// Top 32-bit word of r plus one, inverted: floor(t / (r_top + 1)) for the
+// top bits t of y never exceeds the true quotient floor(y / r).
 #define FR_INV_RTOP1 (1.0 / 811880051.0)  // r_top = 0x30644e72 = 811880050
 
 // Merge the byte-plane partials of two outputs (acc0 -> output k0 in lanes
 // 0..31, acc1 -> k1 in lanes 32..63) and reduce mod r. Lane l holds rows
 // h = 8i + 4*(l/32) + j in register 4i + j (the 32x32 MFMA accumulator
-// layout), i.e. the partials of 32-bit words 2i + l/32. After the swap of
-// the two half-waves each lane holds all 32 partials of its own output,
-// y = sum_h P_h 2^(8h) (a multiple of r keeps it positive, below 2^276).
+// layout), i.e. the partials of 32-bit words 2i + l/32. The seeds lift every
+// partial into [0, 2^26) (their offsets add a multiple of r), so a word
+// group sum_j P_(4w+j) 2^(8j) is an unsigned value below 2^50: three 32x32+64
+// multiply-adds. After the swap of the two half-waves each lane holds the 8
+// word groups of its own output; one add-with-carry per word then gives
+// y = sum_h P_h 2^(8h) < 2^275 as nine words. A quotient estimate from the
+// top 51 bits, at most 2 below floor(y / r), brings y into [0, 3r).
 //
-// The merge runs on exact fp64 integers: a word group sum_j P_(4w+j) 2^(8j)
-// stays below 2^53, and splitting t into floor(t / 2^32) and the remainder
-// is exact. A quotient estimate from the top 52 bits, at most 2 below
-// floor(y / r), then brings y into [0, 3r).
-//
-// The work is cut into kMergeSteps steps of about ten vector instructions,
-// so that it can be spread over the MFMA issue slots of the next outputs.
+// The work is cut into kMergeSteps steps of a few instructions, so that it
+// can be spread over the MFMA issue slots of the next outputs.
 constexpr int kMergeSteps = 16;
 
 struct Merge {
   i32x16 a0, a1;
-  double w0[4], w1[4];
-  double X[4], Y[4];
-  double t, h;
+  uint32_t w8, w16, w24;  // 2^8, 2^16, 2^24 (kernel arguments)
+  uint64_t g0[4], g1[4];
+  uint64_t X[4], Y[4];
   uint32_t y[9];
+  uint32_t c;
   int32_t q;
   uint32_t carry, br;
 
-  __device__ FRNTT_INLINE static double group(const i32x16& a, int i) {
-    return __builtin_fma((double)a[4 * i + 3], 16777216.0,
-            __builtin_fma((double)a[4 * i + 2], 65536.0,
-             __builtin_fma((double)a[4 * i + 1], 256.0, (double)a[4 * i])));
+  __device__ FRNTT_INLINE uint64_t group(const i32x16& a, int i) const {
+    uint64_t x = (uint64_t)(uint32_t)a[4 * i + 1] * w8 + (uint32_t)a[4 * i];
+    x = (uint64_t)(uint32_t)a[4 * i + 2] * w16 + x;
+    return (uint64_t)(uint32_t)a[4 * i + 3] * w24 + x;
   }
   __device__ FRNTT_INLINE void swap(int i) {
-    const uint64_t b0 = __builtin_bit_cast(uint64_t, w0[i]);
-    const uint64_t b1 = __builtin_bit_cast(uint64_t, w1[i]);
-    auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)b0, (uint32_t)b1, false, false);
-    auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(b0 >> 32), (uint32_t)(b1 >> 32), false, false);
-    X[i] = __builtin_bit_cast(double, ((uint64_t)hi[0] << 32) | (uint32_t)lo[0]);  // word 2i
-    Y[i] = __builtin_bit_cast(double, ((uint64_t)hi[1] << 32) | (uint32_t)lo[1]);  // word 2i + 1
+    auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)g0[i], (uint32_t)g1[i], false, false);
+    auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(g0[i] >> 32), (uint32_t)(g1[i] >> 32), false, false);
+    X[i] = ((uint64_t)hi[0] << 32) | (uint32_t)lo[0];  // word 2i
+    Y[i] = ((uint64_t)hi[1] << 32) | (uint32_t)lo[1];  // word 2i + 1
   }
   __device__ FRNTT_INLINE void carry_word(int w) {
-    t = ((w & 1) ? Y[w >> 1] : X[w >> 1]) + (w == 0 ? 0.0 : h);
-    h = __builtin_floor(t * 2.3283064365386963e-10);  // exact floor(t / 2^32)
-    y[w] = (uint32_t)__builtin_fma(h, -4294967296.0, t);
+    const uint64_t s = ((w & 1) ? Y[w >> 1] : X[w >> 1]) + (w == 0 ? 0u : c);
+    y[w] = (uint32_t)s;
+    c = (uint32_t)(s >> 32);
   }
   __device__ FRNTT_INLINE void sub_qr(int i) {
     const uint64_t p = (uint64_t)(uint32_t)q * fr_mod_word(i) + carry;
     carry = (uint32_t)(p >> 32);
     y[i] = subb(y[i], (uint32_t)p, br, &br);
   }
-  // step s of kMergeSteps (s is a constant after unrolling)
-  __device__ FRNTT_INLINE void step(int s) {
-    switch (s) {
-      case 0: case 1: case 2: case 3: w0[s] = group(a0, s); break;
-      case 4: case 5: case 6: case 7: w1[s - 4] = group(a1, s - 4); break;
-      case 8: swap(0); swap(1); break;
-      case 9: swap(2); swap(3); break;
-      case 10: carry_word(0); carry_word(1); break;
-      case 11: carry_word(2); carry_word(3); break;
-      case 12: carry_word(4); carry_word(5); break;
-      case 13:
-        carry_word(6); carry_word(7);
-        y[8] = (uint32_t)h;
-        break;
-      case 14:
-        // quotient estimate from t = y[8] * 2^32 + y[7] (exact in fp64)
-        q = (int32_t)(t * FR_INV_RTOP1) - 1;
-        q = q < 0 ? 0 : q;
-        carry = 0;
-        br = 0;
-        sub_qr(0); sub_qr(1); sub_qr(2); sub_qr(3);
-        break;
-      default: sub_qr(4); sub_qr(5); sub_qr(6); sub_qr(7); break;
+  // step S of kMergeSteps
+  template <int S>
+  __device__ FRNTT_INLINE void step() {
+    if constexpr (S < 4) {
+      g0[S] = group(a0, S);
+    } else if constexpr (S < 8) {
+      g1[S - 4] = group(a1, S - 4);
+    } else if constexpr (S == 8) {
+      swap(0); swap(1);
+    } else if constexpr (S == 9) {
+      swap(2); swap(3);
+    } else if constexpr (S < 13) {
+      carry_word(2 * (S - 10)); carry_word(2 * (S - 10) + 1);
+    } else if constexpr (S == 13) {
+      carry_word(6); carry_word(7);
+      y[8] = c;
+    } else if constexpr (S == 14) {
+      // quotient estimate from the top 51 bits y[8] * 2^32 + y[7] (exact in fp64)
+      const double t = __builtin_fma((double)y[8], 4294967296.0, (double)y[7]);
+      q = (int32_t)(t * FR_INV_RTOP1) - 1;
+      q = q < 0 ? 0 : q;
+      carry = 0;
+      br = 0;
+      sub_qr(0); sub_qr(1); sub_qr(2); sub_qr(3);
+    } else {
+      sub_qr(4); sub_qr(5); sub_qr(6); sub_qr(7);
     }
   }
   __device__ FRNTT_INLINE fr_t result() const {
@@ -261,27 +262,6 @@ __device__ FRNTT_INLINE int level_out_pos(const PassParams& P, const LevelGeom& 
   return (n_next << (P.log_t - g.next_m)) + col;
 }
 
-// Inter-level twiddle, elementwise over the staged tile: the element at
-// next-level position e came from vector nn, digit k of this level and is
-// multiplied by w^(nn * k) of the size-2^(m + q_log) sub-problem. Inputs may
-// be any value below 2^256 (word-scanned operand); outputs are canonical.
-template <int NT>
-__device__ FRNTT_INLINE void level_twiddle(u32x4* lds, const PassParams& P, const DevTables& T,
-                                           const LevelGeom& g) {
-  const int T_el = 1 << P.log_t;
-  const int col_bits = P.log_t - g.next_m;
-  const int nshift = g.q_log - g.next_m;
-#pragma unroll 2
-  for (int e = threadIdx.x; e < T_el; e += NT) {
-    const int n_next = e >> col_bits;
-    const int c2 = (e & ((1 << col_bits) - 1)) >> P.log_g;
-    const int k = (c2 >> g.pprev_log) & ((1 << g.m) - 1);
-    const int nn = (n_next << nshift) + (c2 >> (g.pprev_log + g.m));
-    const fr_t tw = small_tw(T, P.dir, g.m + g.q_log, (uint32_t)(nn * k));
-    lds_st(lds, e, mont_mul(tw, lds_ld(lds, e)));
-  }
-}
-
 // Constant blocks of radix 2^M (RHO x 64 lanes x 16 B of signed digits)
 // followed by the accumulator seeds (RHO x 2 halves x 16 int32), staged in
 // LDS at dst.
@@ -297,59 +277,126 @@ __device__ FRNTT_INLINE void stage_bat(i32x4* dst, const DevTables& T, int dir) 
 template <int M>
 constexpr int bat_lds_size() { return (1 << M) * 72; }  // i32x4 units
 
+// Per-lane work on one output of a pair: the carry merge and, if TW, the
+// inter-level twiddle w^(nn k) of the size-2^(m + q_log) sub-problem
+// (Montgomery product of the merged value, below 3r, with the twiddle), cut
+// into kSteps small steps.
+template <bool TW>
+struct PairWork {
+  static constexpr int kSteps = TW ? kMergeSteps + 11 : kMergeSteps;
+  Merge mg;
+  MontMul mm;
+  fr_t tw;  // twiddle (Montgomery form), loaded when the pair starts
+  fr_t y;   // the output of the pair: below 3r without TW, canonical with it
+
+  template <int S>
+  __device__ FRNTT_INLINE void step() {
+    if constexpr (S < kMergeSteps) {
+      mg.template step<S>();
+      if constexpr (S == kMergeSteps - 1) y = mg.result();
+    } else if constexpr (S == kMergeSteps) {
+      mm.load(tw, y);
+    } else if constexpr (S <= kMergeSteps + 9) {
+      mm.row(S - kMergeSteps - 1);
+    } else {
+      y = mm.finish();
+    }
+  }
+  // steps [S0, S1)
+  template <int S0, int S1>
+  __device__ FRNTT_INLINE void steps() {
+    if constexpr (S0 < S1) {
+      step<S0>();
+      steps<S0 + 1, S1>();
+    }
+  }
+};
+
 // One pipelined step of an MFMA level: issue the 2 x RHO MFMAs of the pair
 // (k0, k0 + 1) of one tile into (n0, n1), seeded with the signed-digit
-// correction and the positive bias, while the merge `mg` of the previous pair
-// (if `merging`) advances by kMergeSteps / RHO steps per input digit. The
-// constant blocks are loaded one digit ahead, and a scheduling barrier after
-// each digit keeps the vector work between the MFMAs, so the matrix and
-// vector pipes of a SIMD overlap within the wave.
-template <int RHO>
-__device__ FRNTT_INLINE void mfma_pair_merge(const i32x4* lds_f, const i32x4* init, const i32x4 (&Bt)[RHO],
-                                             int k0, int lane, int half, i32x16& n0, i32x16& n1, Merge& mg,
-                                             bool merging) {
-  constexpr int SPN = kMergeSteps / RHO;  // merge steps per input digit
+// correction and the row offsets, while the work `wk` on the previous pair
+// (if WORKING) advances through its steps, spread evenly over the MFMA issue
+// slots. The constant blocks (E depends on k n mod RHO only) are read from
+// LDS one digit ahead; a scheduling barrier after each digit keeps the
+// vector work between the MFMAs, so the matrix and vector pipes of a SIMD
+// overlap within the wave.
+template <int RHO, bool WORKING, class W, int N>
+struct DigitLoop {
+  __device__ FRNTT_INLINE static void run(const i32x4* lds_f, const i32x4 (&Bt)[RHO], int k0, int lane,
+                                          i32x16& n0, i32x16& n1, W& wk, i32x4 a0, i32x4 a1) {
+    if constexpr (N < RHO) {
+      constexpr int SLOTS = 2 * RHO;
+      i32x4 p0 = a0, p1 = a1;
+      if constexpr (N + 1 < RHO) {
+        p0 = lds_f[((k0 * (N + 1)) & (RHO - 1)) * 64 + lane];
+        p1 = lds_f[(((k0 + 1) * (N + 1)) & (RHO - 1)) * 64 + lane];
+      }
+      n0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, Bt[N], n0, 0, 0, 0);
+      if constexpr (WORKING) wk.template steps<(2 * N) * W::kSteps / SLOTS, (2 * N + 1) * W::kSteps / SLOTS>();
+      n1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, Bt[N], n1, 0, 0, 0);
+      if constexpr (WORKING) wk.template steps<(2 * N + 1) * W::kSteps / SLOTS, (2 * N + 2) * W::kSteps / SLOTS>();
+      __builtin_amdgcn_sched_barrier(0);
+      DigitLoop<RHO, WORKING, W, N + 1>::run(lds_f, Bt, k0, lane, n0, n1, wk, p0, p1);
+    }
+  }
+};
+
+template <int RHO, bool WORKING, class W>
+__device__ FRNTT_INLINE void mfma_pair_work(const i32x4* lds_f, const i32x4* init, const i32x4 (&Bt)[RHO], int k0,
+                                            int lane, int half, i32x16& n0, i32x16& n1, W& wk) {
   n0 = load_init(init, k0, half);
   n1 = load_init(init, k0 + 1, half);
-  i32x4 a0 = lds_f[lane];  // k * 0 = 0
-  i32x4 a1 = a0;
-#pragma unroll
-  for (int n = 0; n < RHO; ++n) {
-    i32x4 p0 = a0, p1 = a1;
-    if (n + 1 < RHO) {
-      p0 = lds_f[((k0 * (n + 1)) & (RHO - 1)) * 64 + lane];
-      p1 = lds_f[(((k0 + 1) * (n + 1)) & (RHO - 1)) * 64 + lane];
-    }
-    n0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, Bt[n], n0, 0, 0, 0);
-    if (merging) {
-#pragma unroll
-      for (int s = 0; s < (SPN + 1) / 2; ++s) mg.step(n * SPN + s);
-    }
-    n1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, Bt[n], n1, 0, 0, 0);
-    if (merging) {
-#pragma unroll
-      for (int s = (SPN + 1) / 2; s < SPN; ++s) mg.step(n * SPN + s);
-    }
-    __builtin_amdgcn_sched_barrier(0);
-    a0 = p0;
-    a1 = p1;
-  }
+  const i32x4 a = lds_f[lane];  // k * 0 = 0
+  DigitLoop<RHO, WORKING, W, 0>::run(lds_f, Bt, k0, lane, n0, n1, wk, a, a);
 }
+
+// The output pairs of tile T of a wave (tiles unrolled at compile time, so
+// every data-fragment index is static): pair kp is finished while the MFMAs
+// of the next pair (of this tile, or the first of the next) run.
+template <int M, int TPW, bool TW, int T>
+struct TileLoop {
+  __device__ FRNTT_INLINE static void run(u32x4* lds, const i32x4* lds_f, const i32x4* init, const PassParams& P,
+                                          const DevTables& Tb, const LevelGeom& g, const i32x4 (&B)[TPW][1 << M],
+                                          int tile0, int col, int half, int lane, i32x16& n0, i32x16& n1,
+                                          PairWork<TW>& wk) {
+    if constexpr (T < TPW) {
+      constexpr int RHO = 1 << M;
+      constexpr int NKP = RHO / 2;
+      const int v = (tile0 + T) * 32 + col;
+      const int nn = (v >> P.log_g) >> g.pprev_log;
+#pragma unroll 1
+      for (int kp = 0; kp < NKP; ++kp) {
+        const int k = 2 * kp + half;  // this lane's output digit
+        wk.mg.a0 = n0;
+        wk.mg.a1 = n1;
+        if (TW) wk.tw = small_tw(Tb, P.dir, g.m + g.q_log, (uint32_t)(nn * k));
+        if (kp + 1 < NKP) {
+          mfma_pair_work<RHO, true>(lds_f, init, B[T], 2 * kp + 2, lane, half, n0, n1, wk);
+        } else if constexpr (T + 1 < TPW) {
+          mfma_pair_work<RHO, true>(lds_f, init, B[T + 1], 0, lane, half, n0, n1, wk);
+        } else {
+          wk.template steps<0, PairWork<TW>::kSteps>();
+        }
+        lds_st(lds, level_out_pos(P, g, v, k), wk.y);
+      }
+      TileLoop<M, TPW, TW, T + 1>::run(lds, lds_f, init, P, Tb, g, B, tile0, col, half, lane, n0, n1, wk);
+    }
+  }
+};
 
 // One MFMA level. The 2^(log_t - m) vectors form tiles of 32; each of the 8
 // waves takes TPW whole tiles. A wave first loads the data fragments of its
 // tiles (lane l: bytes 16*(l/32)..+15 of vector l%32 for every input digit
 // n), so that after the barrier the level can overwrite LDS in place. The
-// output pairs of a wave form a software pipeline: the MFMAs of pair i + 1
-// run while pair i is merged, reduced below 3r and written (untwiddled) to
-// the position the next level reads. The inter-level twiddle follows as its
-// own elementwise phase.
-template <int M, int TPW>
+// output pairs of a wave form a software pipeline: while the MFMAs of pair
+// i + 1 run, pair i is merged, reduced below 3r, multiplied by its
+// inter-level twiddle (TW: all levels but the last) and written to the
+// position the next level reads.
+template <int M, int TPW, bool TW>
 __device__ FRNTT_INLINE void mfma_level(u32x4* lds, i32x4* blk, const PassParams& P, const DevTables& T,
                                         const LevelGeom& g, bool stage) {
   constexpr int RHO = 1 << M;
   constexpr int NKP = RHO / 2;  // output pairs per tile
-  static_assert(kMergeSteps % RHO == 0, "merge steps spread evenly over the digits");
   const int V = 1 << (P.log_t - M);
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -372,34 +419,21 @@ __device__ FRNTT_INLINE void mfma_level(u32x4* lds, i32x4* blk, const PassParams
     }
   }
   __syncthreads();
-  Merge mg;
+  PairWork<TW> wk;
+  wk.mg.w8 = T.byte_w[0];
+  wk.mg.w16 = T.byte_w[1];
+  wk.mg.w24 = T.byte_w[2];
   i32x16 n0, n1;
-  mfma_pair_merge<RHO>(lds_f, init, B[0], 0, lane, half, n0, n1, mg, false);
-#pragma unroll
-  for (int t = 0; t < TPW; ++t) {
-    const int v = (tile0 + t) * 32 + col;
-#pragma unroll 1
-    for (int kp = 0; kp < NKP; ++kp) {
-      mg.a0 = n0;
-      mg.a1 = n1;
-      const bool more = kp + 1 < NKP || t + 1 < TPW;
-      if (more) {
-        const int tn = kp + 1 < NKP ? t : t + 1;
-        const int kn = kp + 1 < NKP ? 2 * kp + 2 : 0;
-        if (tn == t) mfma_pair_merge<RHO>(lds_f, init, B[t], kn, lane, half, n0, n1, mg, true);
-        else mfma_pair_merge<RHO>(lds_f, init, B[t + 1 < TPW ? t + 1 : t], kn, lane, half, n0, n1, mg, true);
-      } else {
-#pragma unroll
-        for (int st = 0; st < kMergeSteps; ++st) mg.step(st);
-      }
-      lds_st(lds, level_out_pos(P, g, v, 2 * kp + half), mg.result());
-    }
-  }
+  mfma_pair_work<RHO, false>(lds_f, init, B[0], 0, lane, half, n0, n1, wk);
+  TileLoop<M, TPW, TW, 0>::run(lds, lds_f, init, P, T, g, B, tile0, col, half, lane, n0, n1, wk);
   __syncthreads();
-  if (!g.last) {
-    level_twiddle<kMfmaThreads>(lds, P, T, g);
-    __syncthreads();
-  }
+}
+
+template <int M, int TPW>
+__device__ FRNTT_INLINE void mfma_level_any(u32x4* lds, i32x4* blk, const PassParams& P, const DevTables& T,
+                                            const LevelGeom& g) {
+  if (g.last) mfma_level<M, TPW, false>(lds, blk, P, T, g, true);
+  else mfma_level<M, TPW, true>(lds, blk, P, T, g, true);
 }
 
 // Level shapes: 2^(log_t - m - 5) tiles of 32 vectors, TPW = tiles / 8 per
@@ -409,16 +443,16 @@ __device__ FRNTT_INLINE void run_mfma_level(u32x4* lds, i32x4* lds_f, const Pass
                                             const LevelGeom& g) {
   const int tpw = 1 << (P.log_t - g.m - 5 - 3);
   switch (g.m * 16 + tpw) {
-    case 1 * 16 + 8: mfma_level<1, 8>(lds, lds_f, P, T, g, true); break;
-    case 1 * 16 + 4: mfma_level<1, 4>(lds, lds_f, P, T, g, true); break;
-    case 1 * 16 + 2: mfma_level<1, 2>(lds, lds_f, P, T, g, true); break;
-    case 1 * 16 + 1: mfma_level<1, 1>(lds, lds_f, P, T, g, true); break;
-    case 2 * 16 + 4: mfma_level<2, 4>(lds, lds_f, P, T, g, true); break;
-    case 2 * 16 + 2: mfma_level<2, 2>(lds, lds_f, P, T, g, true); break;
-    case 2 * 16 + 1: mfma_level<2, 1>(lds, lds_f, P, T, g, true); break;
-    case 3 * 16 + 2: mfma_level<3, 2>(lds, lds_f, P, T, g, true); break;
-    case 3 * 16 + 1: mfma_level<3, 1>(lds, lds_f, P, T, g, true); break;
-    case 4 * 16 + 1: mfma_level<4, 1>(lds, lds_f, P, T, g, true); break;
+    case 1 * 16 + 8: mfma_level_any<1, 8>(lds, lds_f, P, T, g); break;
+    case 1 * 16 + 4: mfma_level_any<1, 4>(lds, lds_f, P, T, g); break;
+    case 1 * 16 + 2: mfma_level_any<1, 2>(lds, lds_f, P, T, g); break;
+    case 1 * 16 + 1: mfma_level_any<1, 1>(lds, lds_f, P, T, g); break;
+    case 2 * 16 + 4: mfma_level_any<2, 4>(lds, lds_f, P, T, g); break;
+    case 2 * 16 + 2: mfma_level_any<2, 2>(lds, lds_f, P, T, g); break;
+    case 2 * 16 + 1: mfma_level_any<2, 1>(lds, lds_f, P, T, g); break;
+    case 3 * 16 + 2: mfma_level_any<3, 2>(lds, lds_f, P, T, g); break;
+    case 3 * 16 + 1: mfma_level_any<3, 1>(lds, lds_f, P, T, g); break;
+    case 4 * 16 + 1: mfma_level_any<4, 1>(lds, lds_f, P, T, g); break;
     default: break;  // the host only builds supported level shapes
   }
 }
@@ -475,11 +509,13 @@ __device__ FRNTT_INLINE void run_pass_plan(u32x4* lds, i32x4* lds_f, const PassP
   if (M1 != M0) stage_bat<M1, kMfmaThreads>(lds_f + PL::kOff1, T, P.dir);
   load_lines<kMfmaThreads>(lds, P, T, wg);
   __syncthreads();
-  mfma_level<M0, (1 << (LT - M0 - 8))>(lds, lds_f, P, T, level_geom(M0, 0, M1 + M2, M1), false);
-  mfma_level<M1, (1 << (LT - M1 - 8))>(lds, lds_f + PL::kOff1, P, T, level_geom(M1, M0, M2, M2), false);
+  mfma_level<M0, (1 << (LT - M0 - 8)), true>(lds, lds_f, P, T, level_geom(M0, 0, M1 + M2, M1), false);
+  mfma_level<M1, (1 << (LT - M1 - 8)), (M2 > 0)>(lds, lds_f + PL::kOff1, P, T, level_geom(M1, M0, M2, M2),
+                                                 false);
   if (M2 > 0) {
     constexpr int M2c = M2 > 0 ? M2 : 1;
-    mfma_level<M2c, (1 << (LT - M2c - 8))>(lds, lds_f + PL::kOff2, P, T, level_geom(M2, M0 + M1, 0, 0), false);
+    mfma_level<M2c, (1 << (LT - M2c - 8)), false>(lds, lds_f + PL::kOff2, P, T, level_geom(M2, M0 + M1, 0, 0),
+                                                  false);
   }
   store_lines<kMfmaThreads>(lds, P, T, wg, false);
 }

@@ -81,6 +81,10 @@ Layout make_layout() {
 static void fill_tables(uint8_t* h, const Layout& L) {
   Field F;
   const Fe one = host::from_u64(1);
+  // the device Montgomery radix R = 2^261: a table entry for w holds w * R mod r
+  Fe dev_r = one;
+  for (int i = 0; i < 261; ++i) dev_r = host::add(dev_r, dev_r);
+  auto dev_m = [&](const Fe& x) { return F.mul(x, dev_r); };
   Fe w28[2];
   w28[0] = F.root(kMasterLog);
   w28[1] = F.inv(w28[0]);
@@ -90,8 +94,8 @@ static void fill_tables(uint8_t* h, const Layout& L) {
     Fe step_hi = F.pow_u64(w28[d], 1ull << kSplit);
     Fe p = one, q = one;
     for (int j = 0; j < (1 << kSplit); ++j) {
-      put_elem(h + L.tw_lo[d] + 32 * (size_t)j, F.to_m(p));
-      put_elem(h + L.tw_hi[d] + 32 * (size_t)j, F.to_m(q));
+      put_elem(h + L.tw_lo[d] + 32 * (size_t)j, dev_m(p));
+      put_elem(h + L.tw_hi[d] + 32 * (size_t)j, dev_m(q));
       p = F.mul(p, w28[d]);
       q = F.mul(q, step_hi);
     }
@@ -99,7 +103,7 @@ static void fill_tables(uint8_t* h, const Layout& L) {
     Fe w4096 = F.pow_u64(w28[d], 1ull << (kMasterLog - 12));
     p = one;
     for (int j = 0; j < 4096; ++j) {
-      put_elem(h + L.w4096[d] + 32 * (size_t)j, F.to_m(p));
+      put_elem(h + L.w4096[d] + 32 * (size_t)j, dev_m(p));
       p = F.mul(p, w4096);
     }
     // g^(+-j) and g^(+-(2^14 j))
@@ -107,8 +111,8 @@ static void fill_tables(uint8_t* h, const Layout& L) {
     p = one;
     q = one;
     for (int j = 0; j < (1 << kSplit); ++j) {
-      put_elem(h + L.g_lo[d] + 32 * (size_t)j, F.to_m(p));
-      put_elem(h + L.g_hi[d] + 32 * (size_t)j, F.to_m(q));
+      put_elem(h + L.g_lo[d] + 32 * (size_t)j, dev_m(p));
+      put_elem(h + L.g_hi[d] + 32 * (size_t)j, dev_m(q));
       p = F.mul(p, g[d]);
       q = F.mul(q, g_hi_step);
     }
@@ -116,29 +120,23 @@ static void fill_tables(uint8_t* h, const Layout& L) {
   // 2^-L
   Fe half = F.inv(host::from_u64(2)), p = one;
   for (int l = 0; l <= 28; ++l) {
-    put_elem(h + L.ninv + 32 * (size_t)l, F.to_m(p));
+    put_elem(h + L.ninv + 32 * (size_t)l, dev_m(p));
     p = F.mul(p, half);
   }
-  // bias B = floor(2^275 / r) * r = 2^275 - (2^275 mod r), as 35 bytes
-  // (keeps every merged sum positive; B = 0 mod r)
-  Fe rem = one;
-  for (int i = 0; i < 275; ++i) rem = host::add(rem, rem);
-  uint8_t bias[35];
-  {
-    // 2^275 - rem over 5 limbs
-    uint64_t a[5] = {0, 0, 0, 0, 1ull << (275 - 256)};
-    uint64_t br = 0;
-    for (int i = 0; i < 5; ++i) {
-      unsigned __int128 dd = (unsigned __int128)a[i] - (i < 4 ? rem.v[i] : 0) - br;
-      a[i] = (uint64_t)dd;
-      br = (uint64_t)(dd >> 127);
-    }
-    for (int b = 0; b < 35; ++b) bias[b] = (uint8_t)(a[b >> 3] >> (8 * (b & 7)));
+  // Row offsets of the accumulator seeds: row h starts at 2^25 + delta_h,
+  // which lifts every byte-plane partial sum_(n,a) E * u (|.| < 2^25 for
+  // radices up to 32) into [0, 2^26), so the merge runs on unsigned
+  // integers. The delta_h are the bytes of D = -O mod r for
+  // O = 2^25 * sum_h 2^(8h), so the offsets add O + D = 0 (mod r).
+  Fe o_mod = host::from_u64(0), p256 = one;
+  for (int hh = 0; hh < 32; ++hh) {
+    o_mod = host::add(o_mod, p256);
+    for (int s8 = 0; s8 < 8; ++s8) p256 = host::add(p256, p256);
   }
+  for (int s25 = 0; s25 < 25; ++s25) o_mod = host::add(o_mod, o_mod);
+  const Fe dlt = host::sub(host::from_u64(0), o_mod);
   int32_t beta[32];
-  for (int hh = 0; hh < 31; ++hh) beta[hh] = bias[hh];
-  beta[31] = (int32_t)bias[31] | ((int32_t)bias[32] << 8) | ((int32_t)bias[33] << 16) |
-             ((int32_t)bias[34] << 24);
+  for (int hh = 0; hh < 32; ++hh) beta[hh] = (1 << 25) + (int32_t)byte_of(dlt, hh);
   // byte-limb blocks per radix
   for (int d = 0; d < 2; ++d) {
     for (int m = 1; m <= 5; ++m) {
@@ -213,6 +211,9 @@ int build_tables(frntt_ctx* ctx) {
     }
   }
   T.ninv = (const u32x4*)(b + L.ninv);
+  T.byte_w[0] = 1u << 8;
+  T.byte_w[1] = 1u << 16;
+  T.byte_w[2] = 1u << 24;
   return FRNTT_OK;
 }
 
