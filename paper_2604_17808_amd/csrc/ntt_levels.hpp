@@ -79,8 +79,10 @@ __device__ FRNTT_INLINE void load_lines(u32x4* lds, const PassParams& P, const D
 }
 
 // Write output k of every line (found at LDS row k, or bitrev(k) after the
-// butterfly engine) to HBM, with the pass twiddle w^(rest * k) of the
-// size-2^(l+S) sub-problem, or the last pass's N^-1 / g^-k epilogue.
+// butterfly engine) to HBM. The butterfly engine applies here the pass
+// twiddle w^(rest * k) of the size-2^(l+S) sub-problem, or the last pass's
+// N^-1 / N^-1 g^-k epilogue; the MFMA engine has applied them in its last
+// level.
 template <int NT>
 __device__ FRNTT_INLINE void store_lines(const u32x4* lds, const PassParams& P, const DevTables& T, int64_t wg,
                                          bool bitrev) {
@@ -94,17 +96,18 @@ __device__ FRNTT_INLINE void store_lines(const u32x4* lds, const PassParams& P, 
     const int row = bitrev ? (int)(__builtin_bitreverse32((uint32_t)k) >> (32 - P.log_r)) : k;
     fr_t y = lds_ld(lds, row * G + line);
     const LineMap mp = map_line(P, wg * G + line);
-    // y is below 3r after the MFMA engine (canonical after the butterfly):
-    // it is always the word-scanned operand of a product
-    if (!P.is_last) {
+    // y is below 3r after the MFMA engine (canonical after the butterfly)
+    // (the MFMA engine applies the pass twiddle or the epilogue in its last
+    // level and leaves only forward outputs below 3r)
+    if (!bitrev) {
+      if (P.is_last && P.post == 0) y = fr_reduce_3r(y);
+    } else if (!P.is_last) {
       y = mont_mul(pow_tw(T, P.dir, P.log_r + P.log_s, (uint64_t)mp.rest * (uint64_t)k), y);
     } else if (P.post == 1) {
       y = mont_mul(ld_elem(T.ninv, P.log_n), y);
     } else if (P.post == 2) {
       const uint32_t idx = (uint32_t)(mp.poly_off + ((int64_t)k << mp.out_shift));
       y = mont_mul(mont_mul(ld_elem(T.ninv, P.log_n), coset_pow(T, 1, idx)), y);
-    } else if (!bitrev) {
-      y = fr_reduce_3r(y);
     }
     st_elem(P.dst, mp.out_base + ((int64_t)k << mp.out_shift), y);
   }
@@ -277,29 +280,49 @@ __device__ FRNTT_INLINE void stage_bat(i32x4* dst, const DevTables& T, int dir) 
 template <int M>
 constexpr int bat_lds_size() { return (1 << M) * 72; }  // i32x4 units
 
-// Per-lane work on one output of a pair: the carry merge and, if TW, the
-// inter-level twiddle w^(nn k) of the size-2^(m + q_log) sub-problem
-// (Montgomery product of the merged value, below 3r, with the twiddle), cut
-// into kSteps small steps.
-template <bool TW>
+// Per-lane work on one output of a pair, cut into kSteps small steps: the
+// carry merge, then
+//   KIND 0: nothing (last level of a forward or coset transform: the store
+//           reduces y < 3r),
+//   KIND 1: the inter-level twiddle w^(nn k) of the size-2^(m + q_log)
+//           sub-problem (one Montgomery product),
+//   KIND 2: the pass twiddle w^(rest k) of the size-2^(l + S) sub-problem
+//           (last level of a non-last pass; the twiddle is the product of two
+//           table entries: two Montgomery products),
+//   KIND 3: the inverse transform's N^-1 (last level of the last pass),
+//   KIND 4: the coset inverse's N^-1 g^-k (g^-k from two table entries:
+//           three Montgomery products).
+template <int KIND>
 struct PairWork {
-  static constexpr int kSteps = TW ? kMergeSteps + 11 : kMergeSteps;
+  static constexpr int kProducts = KIND == 0 ? 0 : KIND == 1 ? 1 : KIND == 2 ? 2 : KIND == 3 ? 1 : 3;
+  static constexpr int kSteps = kMergeSteps + 11 * kProducts;
   Merge mg;
   MontMul mm;
-  fr_t tw;  // twiddle (Montgomery form), loaded when the pair starts
-  fr_t y;   // the output of the pair: below 3r without TW, canonical with it
+  fr_t tw, tw2, tw3;  // factors (Montgomery form), loaded when the pair starts
+  fr_t y;             // the output of the pair: below 3r for KIND 0, canonical otherwise
 
+  // step Q of a Montgomery product a * b -> out (11 steps)
+  template <int Q>
+  __device__ FRNTT_INLINE void prod(const fr_t& a, const fr_t& b, fr_t& out) {
+    if constexpr (Q == 0) mm.load(a, b);
+    else if constexpr (Q <= 9) mm.row(Q - 1);
+    else out = mm.finish();
+  }
   template <int S>
   __device__ FRNTT_INLINE void step() {
-    if constexpr (S < kMergeSteps) {
+    constexpr int P0 = kMergeSteps, P1 = kMergeSteps + 11, P2 = kMergeSteps + 22;
+    if constexpr (S < P0) {
       mg.template step<S>();
-      if constexpr (S == kMergeSteps - 1) y = mg.result();
-    } else if constexpr (S == kMergeSteps) {
-      mm.load(tw, y);
-    } else if constexpr (S <= kMergeSteps + 9) {
-      mm.row(S - kMergeSteps - 1);
+      if constexpr (S == P0 - 1) y = mg.result();
+    } else if constexpr (KIND == 1 || KIND == 3) {
+      prod<S - P0>(tw, y, y);
+    } else if constexpr (KIND == 2) {
+      if constexpr (S < P1) prod<S - P0>(tw, tw2, tw);
+      else prod<S - P1>(tw, y, y);
     } else {
-      y = mm.finish();
+      if constexpr (S < P1) prod<S - P0>(tw, tw2, tw);          // g^-k
+      else if constexpr (S < P2) prod<S - P1>(tw3, tw, tw);     // N^-1 g^-k
+      else prod<S - P2>(tw, y, y);
     }
   }
   // steps [S0, S1)
@@ -353,33 +376,53 @@ __device__ FRNTT_INLINE void mfma_pair_work(const i32x4* lds_f, const i32x4* ini
 // The output pairs of tile T of a wave (tiles unrolled at compile time, so
 // every data-fragment index is static): pair kp is finished while the MFMAs
 // of the next pair (of this tile, or the first of the next) run.
-template <int M, int TPW, bool TW, int T>
+template <int M, int TPW, int KIND, int T>
 struct TileLoop {
   __device__ FRNTT_INLINE static void run(u32x4* lds, const i32x4* lds_f, const i32x4* init, const PassParams& P,
                                           const DevTables& Tb, const LevelGeom& g, const i32x4 (&B)[TPW][1 << M],
-                                          int tile0, int col, int half, int lane, i32x16& n0, i32x16& n1,
-                                          PairWork<TW>& wk) {
+                                          int tile0, int col, int half, int lane, int64_t wg, i32x16& n0,
+                                          i32x16& n1, PairWork<KIND>& wk) {
     if constexpr (T < TPW) {
       constexpr int RHO = 1 << M;
       constexpr int NKP = RHO / 2;
       const int v = (tile0 + T) * 32 + col;
-      const int nn = (v >> P.log_g) >> g.pprev_log;
+      const int rem = v >> P.log_g;
+      const int nn = rem >> g.pprev_log;                 // KIND 1: the vector's twiddle row
+      const int kk = rem & ((1 << g.pprev_log) - 1);     // KIND 2: earlier output digits
+      // KIND 2: the line's pass-twiddle row; KIND 4: the line's output base
+      // and stride inside its polynomial
+      LineMap mp{};
+      if (KIND == 2 || KIND == 4) mp = map_line(P, wg * (1 << P.log_g) + (v & ((1 << P.log_g) - 1)));
+      const int64_t rest = mp.rest;
 #pragma unroll 1
       for (int kp = 0; kp < NKP; ++kp) {
         const int k = 2 * kp + half;  // this lane's output digit
         wk.mg.a0 = n0;
         wk.mg.a1 = n1;
-        if (TW) wk.tw = small_tw(Tb, P.dir, g.m + g.q_log, (uint32_t)(nn * k));
+        if (KIND == 1) wk.tw = small_tw(Tb, P.dir, g.m + g.q_log, (uint32_t)(nn * k));
+        if (KIND == 2) {
+          const uint64_t e = (uint64_t)rest * (uint64_t)(kk + (k << g.pprev_log));
+          const uint32_t E = (uint32_t)((e << (kMasterLog - P.log_r - P.log_s)) & ((1u << kMasterLog) - 1));
+          wk.tw = ld_elem(Tb.tw_lo[P.dir], E & ((1u << kSplit) - 1));
+          wk.tw2 = ld_elem(Tb.tw_hi[P.dir], E >> kSplit);
+        }
+        if (KIND == 3) wk.tw = ld_elem(Tb.ninv, P.log_n);
+        if (KIND == 4) {
+          const uint32_t idx = (uint32_t)(mp.poly_off + ((int64_t)(kk + (k << g.pprev_log)) << mp.out_shift));
+          wk.tw = ld_elem(Tb.g_lo[1], idx & ((1u << kSplit) - 1));
+          wk.tw2 = ld_elem(Tb.g_hi[1], idx >> kSplit);
+          wk.tw3 = ld_elem(Tb.ninv, P.log_n);
+        }
         if (kp + 1 < NKP) {
           mfma_pair_work<RHO, true>(lds_f, init, B[T], 2 * kp + 2, lane, half, n0, n1, wk);
         } else if constexpr (T + 1 < TPW) {
           mfma_pair_work<RHO, true>(lds_f, init, B[T + 1], 0, lane, half, n0, n1, wk);
         } else {
-          wk.template steps<0, PairWork<TW>::kSteps>();
+          wk.template steps<0, PairWork<KIND>::kSteps>();
         }
         lds_st(lds, level_out_pos(P, g, v, k), wk.y);
       }
-      TileLoop<M, TPW, TW, T + 1>::run(lds, lds_f, init, P, Tb, g, B, tile0, col, half, lane, n0, n1, wk);
+      TileLoop<M, TPW, KIND, T + 1>::run(lds, lds_f, init, P, Tb, g, B, tile0, col, half, lane, wg, n0, n1, wk);
     }
   }
 };
@@ -390,11 +433,11 @@ struct TileLoop {
 // n), so that after the barrier the level can overwrite LDS in place. The
 // output pairs of a wave form a software pipeline: while the MFMAs of pair
 // i + 1 run, pair i is merged, reduced below 3r, multiplied by its
-// inter-level twiddle (TW: all levels but the last) and written to the
-// position the next level reads.
-template <int M, int TPW, bool TW>
+// inter-level or pass twiddle and written to the
+// position the next level reads (KIND: see PairWork).
+template <int M, int TPW, int KIND>
 __device__ FRNTT_INLINE void mfma_level(u32x4* lds, i32x4* blk, const PassParams& P, const DevTables& T,
-                                        const LevelGeom& g, bool stage) {
+                                        const LevelGeom& g, bool stage, int64_t wg) {
   constexpr int RHO = 1 << M;
   constexpr int NKP = RHO / 2;  // output pairs per tile
   const int V = 1 << (P.log_t - M);
@@ -419,45 +462,49 @@ __device__ FRNTT_INLINE void mfma_level(u32x4* lds, i32x4* blk, const PassParams
     }
   }
   __syncthreads();
-  PairWork<TW> wk;
+  PairWork<KIND> wk;
   wk.mg.w8 = T.byte_w[0];
   wk.mg.w16 = T.byte_w[1];
   wk.mg.w24 = T.byte_w[2];
   i32x16 n0, n1;
   mfma_pair_work<RHO, false>(lds_f, init, B[0], 0, lane, half, n0, n1, wk);
-  TileLoop<M, TPW, TW, 0>::run(lds, lds_f, init, P, T, g, B, tile0, col, half, lane, n0, n1, wk);
+  TileLoop<M, TPW, KIND, 0>::run(lds, lds_f, init, P, T, g, B, tile0, col, half, lane, wg, n0, n1, wk);
   __syncthreads();
 }
 
 template <int M, int TPW>
 __device__ FRNTT_INLINE void mfma_level_any(u32x4* lds, i32x4* blk, const PassParams& P, const DevTables& T,
-                                            const LevelGeom& g) {
-  if (g.last) mfma_level<M, TPW, false>(lds, blk, P, T, g, true);
-  else mfma_level<M, TPW, true>(lds, blk, P, T, g, true);
+                                            const LevelGeom& g, int64_t wg) {
+  if (!g.last) mfma_level<M, TPW, 1>(lds, blk, P, T, g, true, wg);
+  else if (!P.is_last) mfma_level<M, TPW, 2>(lds, blk, P, T, g, true, wg);
+  else if (P.post == 1) mfma_level<M, TPW, 3>(lds, blk, P, T, g, true, wg);
+  else if (P.post == 2) mfma_level<M, TPW, 4>(lds, blk, P, T, g, true, wg);
+  else mfma_level<M, TPW, 0>(lds, blk, P, T, g, true, wg);
 }
 
 // Level shapes: 2^(log_t - m - 5) tiles of 32 vectors, TPW = tiles / 8 per
 // wave (the host admits only levels with at least 8 tiles and TPW * RHO <= 16,
 // so a wave's data fragments take at most 64 registers).
 __device__ FRNTT_INLINE void run_mfma_level(u32x4* lds, i32x4* lds_f, const PassParams& P, const DevTables& T,
-                                            const LevelGeom& g) {
+                                            const LevelGeom& g, int64_t wg) {
   const int tpw = 1 << (P.log_t - g.m - 5 - 3);
   switch (g.m * 16 + tpw) {
-    case 1 * 16 + 8: mfma_level_any<1, 8>(lds, lds_f, P, T, g); break;
-    case 1 * 16 + 4: mfma_level_any<1, 4>(lds, lds_f, P, T, g); break;
-    case 1 * 16 + 2: mfma_level_any<1, 2>(lds, lds_f, P, T, g); break;
-    case 1 * 16 + 1: mfma_level_any<1, 1>(lds, lds_f, P, T, g); break;
-    case 2 * 16 + 4: mfma_level_any<2, 4>(lds, lds_f, P, T, g); break;
-    case 2 * 16 + 2: mfma_level_any<2, 2>(lds, lds_f, P, T, g); break;
-    case 2 * 16 + 1: mfma_level_any<2, 1>(lds, lds_f, P, T, g); break;
-    case 3 * 16 + 2: mfma_level_any<3, 2>(lds, lds_f, P, T, g); break;
-    case 3 * 16 + 1: mfma_level_any<3, 1>(lds, lds_f, P, T, g); break;
-    case 4 * 16 + 1: mfma_level_any<4, 1>(lds, lds_f, P, T, g); break;
+    case 1 * 16 + 8: mfma_level_any<1, 8>(lds, lds_f, P, T, g, wg); break;
+    case 1 * 16 + 4: mfma_level_any<1, 4>(lds, lds_f, P, T, g, wg); break;
+    case 1 * 16 + 2: mfma_level_any<1, 2>(lds, lds_f, P, T, g, wg); break;
+    case 1 * 16 + 1: mfma_level_any<1, 1>(lds, lds_f, P, T, g, wg); break;
+    case 2 * 16 + 4: mfma_level_any<2, 4>(lds, lds_f, P, T, g, wg); break;
+    case 2 * 16 + 2: mfma_level_any<2, 2>(lds, lds_f, P, T, g, wg); break;
+    case 2 * 16 + 1: mfma_level_any<2, 1>(lds, lds_f, P, T, g, wg); break;
+    case 3 * 16 + 2: mfma_level_any<3, 2>(lds, lds_f, P, T, g, wg); break;
+    case 3 * 16 + 1: mfma_level_any<3, 1>(lds, lds_f, P, T, g, wg); break;
+    case 4 * 16 + 1: mfma_level_any<4, 1>(lds, lds_f, P, T, g, wg); break;
     default: break;  // the host only builds supported level shapes
   }
 }
 
-__device__ FRNTT_INLINE void mfma_levels(u32x4* lds, i32x4* lds_f, const PassParams& P, const DevTables& T) {
+__device__ FRNTT_INLINE void mfma_levels(u32x4* lds, i32x4* lds_f, const PassParams& P, const DevTables& T,
+                                         int64_t wg) {
   int pprev = 0;
   int rest = P.log_r;
   for (int lev = 0; lev < P.nlev; ++lev) {
@@ -468,7 +515,7 @@ __device__ FRNTT_INLINE void mfma_levels(u32x4* lds, i32x4* lds_f, const PassPar
     g.q_log = rest;
     g.next_m = lev + 1 < P.nlev ? P.lev_log[lev + 1] : 0;
     g.last = lev + 1 == P.nlev;
-    run_mfma_level(lds, lds_f, P, T, g);
+    run_mfma_level(lds, lds_f, P, T, g, wg);
     pprev += g.m;
   }
 }
@@ -483,8 +530,12 @@ template <int M0, int M1, int M2>
 struct PassPlan {
   static constexpr int kLevels = M2 > 0 ? 3 : 2;
   static_assert(M1 == M0 || M2 == 0 || M2 == M0 || M2 == M1, "at most two distinct radices");
+  // LDS offsets of the blocks of each level: the first radix at 0, the
+  // other distinct radix (M1, or M2 when M1 == M0) after it
   static constexpr int kOff1 = M1 == M0 ? 0 : bat_lds_size<M0>();
-  static constexpr int kOff2 = M2 == M0 ? 0 : kOff1;
+  static constexpr int kOff2 = M2 == M0 ? 0 : (M2 == M1 ? kOff1 : bat_lds_size<M0>());
+  static constexpr bool kStage1 = M1 != M0;
+  static constexpr bool kStage2 = M2 > 0 && M2 != M0 && M2 != M1;
   static constexpr int kLds = bat_lds_size<M0>() + (M1 == M0 ? 0 : bat_lds_size<M1>()) +
                               (M2 > 0 && M2 != M0 && M2 != M1 ? bat_lds_size<M2>() : 0);
 };
@@ -500,22 +551,34 @@ __device__ FRNTT_INLINE LevelGeom level_geom(int m, int pprev, int q, int next_m
   return g;
 }
 
+// Last level of a planned pass: the pass twiddle, or the last pass's
+// epilogue, rides on it.
+template <int M>
+__device__ FRNTT_INLINE void plan_last_level(u32x4* lds, i32x4* blk, const PassParams& P, const DevTables& T,
+                                             const LevelGeom& g, int64_t wg) {
+  constexpr int TPW = 1 << (kMaxLogT - M - 8);
+  if (!P.is_last) mfma_level<M, TPW, 2>(lds, blk, P, T, g, false, wg);
+  else if (P.post == 1) mfma_level<M, TPW, 3>(lds, blk, P, T, g, false, wg);
+  else if (P.post == 2) mfma_level<M, TPW, 4>(lds, blk, P, T, g, false, wg);
+  else mfma_level<M, TPW, 0>(lds, blk, P, T, g, false, wg);
+}
+
 template <int M0, int M1, int M2>
 __device__ FRNTT_INLINE void run_pass_plan(u32x4* lds, i32x4* lds_f, const PassParams& P, const DevTables& T,
                                            int64_t wg) {
   using PL = PassPlan<M0, M1, M2>;
   constexpr int LT = kMaxLogT;  // staged elements 2^12
   stage_bat<M0, kMfmaThreads>(lds_f, T, P.dir);
-  if (M1 != M0) stage_bat<M1, kMfmaThreads>(lds_f + PL::kOff1, T, P.dir);
+  if constexpr (PL::kStage1) stage_bat<M1, kMfmaThreads>(lds_f + PL::kOff1, T, P.dir);
+  if constexpr (PL::kStage2) stage_bat<(M2 > 0 ? M2 : 1), kMfmaThreads>(lds_f + PL::kOff2, T, P.dir);
   load_lines<kMfmaThreads>(lds, P, T, wg);
   __syncthreads();
-  mfma_level<M0, (1 << (LT - M0 - 8)), true>(lds, lds_f, P, T, level_geom(M0, 0, M1 + M2, M1), false);
-  mfma_level<M1, (1 << (LT - M1 - 8)), (M2 > 0)>(lds, lds_f + PL::kOff1, P, T, level_geom(M1, M0, M2, M2),
-                                                 false);
-  if (M2 > 0) {
-    constexpr int M2c = M2 > 0 ? M2 : 1;
-    mfma_level<M2c, (1 << (LT - M2c - 8)), false>(lds, lds_f + PL::kOff2, P, T, level_geom(M2, M0 + M1, 0, 0),
-                                                  false);
+  mfma_level<M0, (1 << (LT - M0 - 8)), 1>(lds, lds_f, P, T, level_geom(M0, 0, M1 + M2, M1), false, wg);
+  if constexpr (M2 > 0) {
+    mfma_level<M1, (1 << (LT - M1 - 8)), 1>(lds, lds_f + PL::kOff1, P, T, level_geom(M1, M0, M2, M2), false, wg);
+    plan_last_level<M2>(lds, lds_f + PL::kOff2, P, T, level_geom(M2, M0 + M1, 0, 0), wg);
+  } else {
+    plan_last_level<M1>(lds, lds_f + PL::kOff1, P, T, level_geom(M1, M0, 0, 0), wg);
   }
   store_lines<kMfmaThreads>(lds, P, T, wg, false);
 }
@@ -529,7 +592,7 @@ __device__ FRNTT_INLINE void run_pass(u32x4* lds, i32x4* lds_f, const PassParams
   load_lines<NT>(lds, P, T, wg);
   __syncthreads();
   const bool use_mfma = ENGINE == 1 || (ENGINE == 2 && P.engine == 1);
-  if (use_mfma) mfma_levels(lds, lds_f, P, T);
+  if (use_mfma) mfma_levels(lds, lds_f, P, T, wg);
   else bfly_stages<NT>(lds, P, T);
   store_lines<NT>(lds, P, T, wg, !use_mfma);
 }

@@ -96,17 +96,29 @@ def test_batch_counts(ctx, algo, batch):
 
 @pytest.mark.parametrize("algo", ALGOS, ids=ALGO_IDS)
 @pytest.mark.parametrize("plan", [[8, 8], [10, 6], [6, 10], [4, 12], [12, 4], [4, 6, 6], [6, 5, 5],
-                                  [2, 2, 12]])
+                                  [2, 2, 12], [11, 5], [5, 11], [9, 7], [7, 9]])
 def test_plans_bit_identical(ctx, algo, plan):
     """Every pass split of 2^16 gives the same bytes as the oracle."""
     _say(f"plan algo={algo} plan={plan}")
     ctx.set_plan(algo, 16, plan)
     try:
         x = inputs(11, 16, 2)
-        for kind in (0, 3):
+        for kind in range(4):
             assert np.array_equal(run(ctx, x, 16, kind, algo), cref.transform(x, 16, kind))
     finally:
         ctx.set_plan(algo, 16, [])
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2, 3])
+@pytest.mark.parametrize("log_n,batch", [(12, 1), (11, 2), (10, 4), (9, 8), (8, 16), (7, 32), (6, 64), (5, 128),
+                                         (11, 4), (10, 2)])
+def test_full_tile_level_shapes(ctx, log_n, batch, kind):
+    """Single-pass transforms whose lines fill a 4096-element tile: every
+    level split of the matrix form (radix 2^5 .. 2^12) and every epilogue."""
+    _say(f"tile shapes log_n={log_n} batch={batch} kind={kind}")
+    x = inputs(200 + log_n, log_n, batch)
+    got = run(ctx, x, log_n, kind, fr.ALGO_FOURSTEP_MFMA)
+    assert np.array_equal(got, cref.transform(x, log_n, kind))
 
 
 @pytest.mark.parametrize("pattern", ["zeros", "rminus1", "onehot", "alternating"])
