@@ -156,6 +156,18 @@ int frntt_check_inputs(frntt_ctx *ctx);
 /* Scratch bytes a transform of this size needs (informational). */
 size_t frntt_scratch_bytes(int log_n, int batch);
 
+/* Build now the tables a transform of 2^log_n elements of this kind will use
+ * (the twiddle table of every pass but the last, w^(rest*k) of the pass's
+ * sub-problem: the pass twiddles of the 3-step / 5-step decomposition, Eq. 1,
+ * which the paper generates offline), so that later calls allocate nothing
+ * for them. Otherwise they are built on first use. Synchronous. Errors:
+ * EINVAL, ERANGE, ENOMEM, EHIP. */
+int frntt_prepare(frntt_ctx *ctx, int log_n, int kind);
+
+/* Device bytes held by the context's tables, including the pass-twiddle
+ * tables built so far. */
+size_t frntt_table_bytes(const frntt_ctx *ctx);
+
 /* Last hipError_t seen by the context (0 if none). */
 int frntt_last_hip_error(const frntt_ctx *ctx);
 /* Static description of a status code. */

@@ -152,7 +152,7 @@ static int pass_log_g(const Plan& plan, int p, int log_n, int batch) {
   return std::max(lg, 0);
 }
 
-int build_passes(const frntt_ctx* ctx, const Plan& plan_in, int log_n, int batch, int kind, void* data,
+int build_passes(frntt_ctx* ctx, const Plan& plan_in, int log_n, int batch, int kind, void* data,
                  void* scratch, std::vector<PassParams>* out, int algo) {
   Plan plan = plan_in;
   out->clear();
@@ -189,10 +189,67 @@ int build_passes(const frntt_ctx* ctx, const Plan& plan_in, int log_n, int batch
     const int64_t lines = ((int64_t)batch << log_n) >> l;
     P.wg_count = lines >> lg;
     P.xcd_remap = 1;
+    P.pass_tw = nullptr;
+    if (!last) {
+      int rc = FRNTT_OK;
+      P.pass_tw = pass_table(ctx, dir, l, s, &rc);
+      if (rc != FRNTT_OK) return rc;
+    }
     out->push_back(P);
     d += l;
   }
   return FRNTT_OK;
+}
+
+const u32x4* pass_table(frntt_ctx* ctx, int dir, int log_r, int log_s, int* rc) {
+  *rc = FRNTT_OK;
+  if (log_r + log_s > kPassTableMaxLog) return nullptr;
+  const int key = (dir << 16) | (log_r << 8) | log_s;
+  std::lock_guard<std::mutex> lk(ctx->tw_mu);
+  auto it = ctx->pass_tw.find(key);
+  if (it != ctx->pass_tw.end()) return (const u32x4*)it->second;
+  const size_t bytes = (size_t)32 << (log_r + log_s);
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    set_hip_error(ctx, e);
+    *rc = FRNTT_ENOMEM;
+    return nullptr;
+  }
+  // built once, on a private stream, before any transform uses it
+  hipStream_t st = nullptr;
+  e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+  if (e == hipSuccess) {
+    const int64_t n = 1ll << (log_r + log_s);
+    const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(pass_twiddle_kernel, dim3(grid), dim3(256), 0, st, (u32x4*)p, ctx->tables, dir, log_r,
+                       log_s);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    hipStreamDestroy(st);
+  }
+  if (e != hipSuccess) {
+    hipFree(p);
+    *rc = set_hip_error(ctx, e);
+    return nullptr;
+  }
+  ctx->pass_tw[key] = p;
+  ctx->table_bytes += bytes;
+  return (const u32x4*)p;
+}
+
+size_t pending_pass_table_bytes(frntt_ctx* ctx, const Plan& plan, int kind) {
+  const int dir = (kind == FRNTT_INV || kind == FRNTT_COSET_INV) ? 1 : 0;
+  size_t bytes = 0;
+  std::lock_guard<std::mutex> lk(ctx->tw_mu);
+  for (int p = 0; p + 1 < plan.n_pass; ++p) {
+    int s = 0;
+    for (int q = p + 1; q < plan.n_pass; ++q) s += plan.pass_log[q];
+    const int l = plan.pass_log[p];
+    if (l + s > kPassTableMaxLog) continue;
+    if (!ctx->pass_tw.count((dir << 16) | (l << 8) | s)) bytes += (size_t)32 << (l + s);
+  }
+  return bytes;
 }
 
 int get_scratch(frntt_ctx* ctx, hipStream_t stream, size_t bytes, void** out) {
@@ -341,6 +398,7 @@ int frntt_ctx_destroy(frntt_ctx* ctx) {
     }
     if (ctx->valid_flag) hipFree(ctx->valid_flag);
     if (ctx->table_mem) hipFree(ctx->table_mem);
+    for (auto& kv : ctx->pass_tw) hipFree(kv.second);
   }
   delete ctx;
   return FRNTT_OK;
@@ -411,6 +469,20 @@ size_t frntt_scratch_bytes(int log_n, int batch) {
   default_pass_split(log_n, &n_pass, pl);
   return scratch_bytes_for(log_n, batch, n_pass);
 }
+
+int frntt_prepare(frntt_ctx* ctx, int log_n, int kind) {
+  if (!ctx || kind < FRNTT_FWD || kind > FRNTT_COSET_INV) return FRNTT_EINVAL;
+  if (log_n < 0 || log_n > ctx->max_log_n) return FRNTT_ERANGE;
+  DeviceGuard guard(ctx->device);
+  for (int algo = FRNTT_ALGO_BUTTERFLY; algo <= FRNTT_ALGO_FOURSTEP_MFMA; ++algo) {
+    std::vector<PassParams> tmp;
+    const int rc = build_passes(ctx, plan_for(ctx, algo, log_n), log_n, 1, kind, nullptr, nullptr, &tmp, algo);
+    if (rc != FRNTT_OK) return rc;
+  }
+  return FRNTT_OK;
+}
+
+size_t frntt_table_bytes(const frntt_ctx* ctx) { return ctx ? ctx->table_bytes.load() : 0; }
 
 int frntt_generate(frntt_ctx* ctx, void* data, uint64_t seed, uint64_t stream_id, uint64_t start,
                    uint64_t count, void* stream) {

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <string>
@@ -20,6 +21,7 @@ __global__ void generate_kernel(u32x4* out, uint64_t seed, uint64_t stream_id, u
                                 uint64_t count);
 __global__ void validate_kernel(const u32x4* data, uint64_t count, unsigned int* flag);
 __global__ void zero_words_kernel(unsigned int* p, int64_t n);
+__global__ void pass_twiddle_kernel(u32x4* dst, DevTables T, int dir, int log_r, int log_s);
 
 // Decomposition of one transform size into passes and levels.
 struct Plan {
@@ -69,7 +71,7 @@ struct frntt_ctx {
   int cu_count = 0;
   mutable int last_hip_error = 0;
   void* table_mem = nullptr;       // single device allocation holding all tables
-  size_t table_bytes = 0;
+  std::atomic<size_t> table_bytes{0};  // all context tables, including pass-twiddle tables
   frntt::DevTables tables{};
   unsigned int* valid_flag = nullptr;  // device flag for FRNTT_VALIDATE
   // plan overrides [algo][log_n]
@@ -81,6 +83,9 @@ struct frntt_ctx {
   std::map<hipStream_t, frntt::Scratch> scratch;
   std::vector<frntt::GraphEntry> graphs;
   std::map<hipStream_t, frntt::BatchBuffers> batch_bufs;
+  // pass-twiddle tables, built on first use: key (dir, log_r, log_s)
+  std::mutex tw_mu;
+  std::map<int, void*> pass_tw;
 };
 
 namespace frntt {
@@ -89,8 +94,17 @@ int set_hip_error(const frntt_ctx* ctx, hipError_t e);
 // Default or overridden plan for (algo, log_n); algo must be BUTTERFLY or MFMA.
 Plan plan_for(const frntt_ctx* ctx, int algo, int log_n);
 // Build the per-pass launch parameters of one transform.
-int build_passes(const frntt_ctx* ctx, const Plan& plan, int log_n, int batch, int kind,
+int build_passes(frntt_ctx* ctx, const Plan& plan, int log_n, int batch, int kind,
                  void* data, void* scratch, std::vector<PassParams>* out, int algo);
+// Pass-twiddle table w_(2^(log_r + log_s))^(rest * k) at [k][rest] for a
+// non-last pass (built and cached on first use), or nullptr when it would
+// exceed kPassTableMaxLog entries (the pass then forms each twiddle from the
+// split tables).
+constexpr int kPassTableMaxLog = 25;
+const u32x4* pass_table(frntt_ctx* ctx, int dir, int log_r, int log_s, int* rc);
+// Bytes of the pass-twiddle tables a transform with this plan and kind would
+// still have to build.
+size_t pending_pass_table_bytes(frntt_ctx* ctx, const Plan& plan, int kind);
 int effective_algo(const frntt_ctx* ctx, int log_n, int requested);
 size_t scratch_bytes_for(int log_n, int batch, int n_pass);
 int get_scratch(frntt_ctx* ctx, hipStream_t stream, size_t bytes, void** out);

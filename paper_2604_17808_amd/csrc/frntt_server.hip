@@ -279,6 +279,19 @@ int frntt_server_create(frntt_server** out, frntt_ctx* ctx, size_t hbm_budget_by
 int frntt_server_submit(frntt_server* s, int kind, int log_n, uint64_t data_seed, uint64_t* ticket) {
   if (!s || !ticket || kind < FRNTT_FWD || kind > FRNTT_COSET_INV) return FRNTT_EINVAL;
   if (log_n < 1 || log_n > s->ctx->max_log_n) return FRNTT_ERANGE;
+  {
+    // the pass-twiddle tables this request will use count against the
+    // budget from the start: a request that could never fit is refused
+    // before anything is built; otherwise they are built now (once per size
+    // and direction)
+    const int algo = frntt::effective_algo(s->ctx, log_n, FRNTT_ALGO_AUTO);
+    const frntt::Plan plan = frntt::plan_for(s->ctx, algo, log_n);
+    const size_t extra = frntt::pending_pass_table_bytes(s->ctx, plan, kind);
+    if (request_bytes(log_n) + s->ctx->table_bytes + extra > s->budget) return FRNTT_EBUSY;
+    std::vector<frntt::PassParams> tmp;
+    const int rc = frntt::build_passes(s->ctx, plan, log_n, 1, kind, nullptr, nullptr, &tmp, algo);
+    if (rc != FRNTT_OK) return rc;
+  }
   if (request_bytes(log_n) + s->ctx->table_bytes > s->budget) return FRNTT_EBUSY;
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->stop) return FRNTT_ESTATE;

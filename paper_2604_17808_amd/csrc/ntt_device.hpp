@@ -60,6 +60,7 @@ struct PassParams {
   int coset_pre;    // first pass of a coset transform: x_n *= g^n on load
   int post;         // last pass: 0 none, 1 scale by N^-1, 2 scale by N^-1 g^-k
   int xcd_remap;    // map consecutive logical workgroups onto one XCD
+  const u32x4* pass_tw;  // non-last pass: table of its twiddles at [k][rest], or nullptr
 };
 
 // Descriptor tables of one persistent batch launch (see ntt_batch_kernel).

@@ -102,7 +102,9 @@ __device__ FRNTT_INLINE void store_lines(const u32x4* lds, const PassParams& P, 
     if (!bitrev) {
       if (P.is_last && P.post == 0) y = fr_reduce_3r(y);
     } else if (!P.is_last) {
-      y = mont_mul(pow_tw(T, P.dir, P.log_r + P.log_s, (uint64_t)mp.rest * (uint64_t)k), y);
+      const fr_t tw = P.pass_tw ? ld_elem(P.pass_tw, ((int64_t)k << P.log_s) + mp.rest)
+                                : pow_tw(T, P.dir, P.log_r + P.log_s, (uint64_t)mp.rest * (uint64_t)k);
+      y = mont_mul(tw, y);
     } else if (P.post == 1) {
       y = mont_mul(ld_elem(T.ninv, P.log_n), y);
     } else if (P.post == 2) {
@@ -291,10 +293,12 @@ constexpr int bat_lds_size() { return (1 << M) * 72; }  // i32x4 units
 //           table entries: two Montgomery products),
 //   KIND 3: the inverse transform's N^-1 (last level of the last pass),
 //   KIND 4: the coset inverse's N^-1 g^-k (g^-k from two table entries:
-//           three Montgomery products).
+//           three Montgomery products),
+//   KIND 5: the pass twiddle read from the pass's twiddle table (one
+//           Montgomery product).
 template <int KIND>
 struct PairWork {
-  static constexpr int kProducts = KIND == 0 ? 0 : KIND == 1 ? 1 : KIND == 2 ? 2 : KIND == 3 ? 1 : 3;
+  static constexpr int kProducts = KIND == 0 ? 0 : KIND == 2 ? 2 : KIND == 4 ? 3 : 1;
   static constexpr int kSteps = kMergeSteps + 11 * kProducts;
   Merge mg;
   MontMul mm;
@@ -314,7 +318,7 @@ struct PairWork {
     if constexpr (S < P0) {
       mg.template step<S>();
       if constexpr (S == P0 - 1) y = mg.result();
-    } else if constexpr (KIND == 1 || KIND == 3) {
+    } else if constexpr (KIND == 1 || KIND == 3 || KIND == 5) {
       prod<S - P0>(tw, y, y);
     } else if constexpr (KIND == 2) {
       if constexpr (S < P1) prod<S - P0>(tw, tw2, tw);
@@ -389,10 +393,10 @@ struct TileLoop {
       const int rem = v >> P.log_g;
       const int nn = rem >> g.pprev_log;                 // KIND 1: the vector's twiddle row
       const int kk = rem & ((1 << g.pprev_log) - 1);     // KIND 2: earlier output digits
-      // KIND 2: the line's pass-twiddle row; KIND 4: the line's output base
+      // KIND 2, 5: the line's pass-twiddle row; KIND 4: the line's output base
       // and stride inside its polynomial
       LineMap mp{};
-      if (KIND == 2 || KIND == 4) mp = map_line(P, wg * (1 << P.log_g) + (v & ((1 << P.log_g) - 1)));
+      if (KIND == 2 || KIND == 4 || KIND == 5) mp = map_line(P, wg * (1 << P.log_g) + (v & ((1 << P.log_g) - 1)));
       const int64_t rest = mp.rest;
 #pragma unroll 1
       for (int kp = 0; kp < NKP; ++kp) {
@@ -406,6 +410,7 @@ struct TileLoop {
           wk.tw = ld_elem(Tb.tw_lo[P.dir], E & ((1u << kSplit) - 1));
           wk.tw2 = ld_elem(Tb.tw_hi[P.dir], E >> kSplit);
         }
+        if (KIND == 5) wk.tw = ld_elem(P.pass_tw, ((int64_t)(kk + (k << g.pprev_log)) << P.log_s) + rest);
         if (KIND == 3) wk.tw = ld_elem(Tb.ninv, P.log_n);
         if (KIND == 4) {
           const uint32_t idx = (uint32_t)(mp.poly_off + ((int64_t)(kk + (k << g.pprev_log)) << mp.out_shift));
@@ -476,6 +481,7 @@ template <int M, int TPW>
 __device__ FRNTT_INLINE void mfma_level_any(u32x4* lds, i32x4* blk, const PassParams& P, const DevTables& T,
                                             const LevelGeom& g, int64_t wg) {
   if (!g.last) mfma_level<M, TPW, 1>(lds, blk, P, T, g, true, wg);
+  else if (!P.is_last && P.pass_tw) mfma_level<M, TPW, 5>(lds, blk, P, T, g, true, wg);
   else if (!P.is_last) mfma_level<M, TPW, 2>(lds, blk, P, T, g, true, wg);
   else if (P.post == 1) mfma_level<M, TPW, 3>(lds, blk, P, T, g, true, wg);
   else if (P.post == 2) mfma_level<M, TPW, 4>(lds, blk, P, T, g, true, wg);
@@ -557,7 +563,8 @@ template <int M>
 __device__ FRNTT_INLINE void plan_last_level(u32x4* lds, i32x4* blk, const PassParams& P, const DevTables& T,
                                              const LevelGeom& g, int64_t wg) {
   constexpr int TPW = 1 << (kMaxLogT - M - 8);
-  if (!P.is_last) mfma_level<M, TPW, 2>(lds, blk, P, T, g, false, wg);
+  if (!P.is_last && P.pass_tw) mfma_level<M, TPW, 5>(lds, blk, P, T, g, false, wg);
+  else if (!P.is_last) mfma_level<M, TPW, 2>(lds, blk, P, T, g, false, wg);
   else if (P.post == 1) mfma_level<M, TPW, 3>(lds, blk, P, T, g, false, wg);
   else if (P.post == 2) mfma_level<M, TPW, 4>(lds, blk, P, T, g, false, wg);
   else mfma_level<M, TPW, 0>(lds, blk, P, T, g, false, wg);

@@ -67,4 +67,16 @@ __global__ void zero_words_kernel(unsigned int* p, int64_t n) {
   if (i < n) p[i] = 0;
 }
 
+// Twiddles of a non-last pass, w_(2^(log_r + log_s))^(rest * k) in
+// Montgomery form, at index k * 2^log_s + rest (k < 2^log_r, rest < 2^log_s):
+// the stores of a pass then read them contiguously along its lines.
+__global__ void pass_twiddle_kernel(u32x4* dst, DevTables T, int dir, int log_r, int log_s) {
+  const int64_t n = 1ll << (log_r + log_s);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = (uint64_t)i >> log_s;
+    const uint64_t rest = (uint64_t)i & ((1ull << log_s) - 1);
+    st_elem(dst, i, pow_tw(T, dir, log_r + log_s, rest * k));
+  }
+}
+
 }  // namespace frntt

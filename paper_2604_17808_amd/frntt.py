@@ -54,6 +54,8 @@ SIGNATURES = {
     "frntt_generate": (_i, [_vp, _vp, _u64, _u64, _u64, _u64, _vp]),
     "frntt_check_inputs": (_i, [_vp]),
     "frntt_scratch_bytes": (_sz, [_i, _i]),
+    "frntt_prepare": (_i, [_vp, _i, _i]),
+    "frntt_table_bytes": (_sz, [_vp]),
     "frntt_last_hip_error": (_i, [_vp]),
     "frntt_strerror": (ctypes.c_char_p, [_i]),
     "frntt_server_create": (_i, [ctypes.POINTER(_vp), _vp, _sz, _i]),
@@ -200,6 +202,12 @@ class Context:
     def generate(self, ptr: int, seed: int, stream_id: int, start: int, count: int, stream: int = 0):
         return _check(lib().frntt_generate(self._h, ptr, seed, stream_id, start, count, stream),
                       "frntt_generate")
+
+    def prepare(self, log_n: int, kind: int = FWD):
+        return _check(lib().frntt_prepare(self._h, log_n, kind), "frntt_prepare")
+
+    def table_bytes(self) -> int:
+        return lib().frntt_table_bytes(self._h)
 
     def check_inputs(self) -> int:
         return lib().frntt_check_inputs(self._h)

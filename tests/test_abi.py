@@ -46,6 +46,8 @@ def test_strerror_and_sizes():
     assert L.frntt_scratch_bytes(10, 4) == 0            # one pass: in place
     assert L.frntt_scratch_bytes(20, 1) == 32 << 20     # two passes: one copy
     assert L.frntt_scratch_bytes(-1, 1) == 0
+    assert L.frntt_prepare(None, 10, 0) == B.EINVAL
+    assert L.frntt_table_bytes(None) == 0
 
 
 def test_argument_errors_without_device():

@@ -86,7 +86,8 @@ def test_server_release_on_done(ctx):
 
 
 def test_server_destroy_cancels_queued(ctx):
-    srv = fr.Server(ctx, (8 << 20) + (5 << 20), slots=1)
+    ctx.prepare(16, 0)
+    srv = fr.Server(ctx, ctx.table_bytes() + (5 << 20), slots=1)
     for k in range(6):
         srv.submit(0, 16, 2)                          # only one fits; the rest stay queued
     time.sleep(0.2)
@@ -94,7 +95,9 @@ def test_server_destroy_cancels_queued(ctx):
 
 
 def test_server_budget_and_errors(ctx):
-    tables = 8 << 20                                  # context tables are a few MiB
+    for kind in range(3):
+        ctx.prepare(16, kind)                         # tables the requests below use
+    tables = ctx.table_bytes()
     budget = tables + (6 << 20)
     srv = fr.Server(ctx, budget, slots=2)
     try:
