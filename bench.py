@@ -29,6 +29,7 @@ INT8_PEAK_TOPS = 5000.0        # MI355X dense int8 MFMA, TOP/s
 MAD_PEAK_TMADS = 256 * 64 * 2.4e9 / 1e12
 MADS_PER_PRODUCT = 162         # Montgomery product on nine 29-bit limbs (9 rows x 18)
 MADS_PER_MERGE = 20            # carry merge: 12 for the word groups + 8 for the quotient step
+PASS_TABLE_MAX_LOG = 25        # the library keeps a twiddle table for non-last passes up to 2^25 entries
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_mfma_fwd_2e20.txt")
 KERNEL_SOURCES = ["fr.hpp", "ntt_device.hpp", "ntt_levels.hpp", "ntt_pass_mfma.hip"]
 
@@ -71,14 +72,20 @@ def algorithmic_work(plan, kind=0):
         levs = level_split(l)
         mads = MADS_PER_MERGE * len(levs) + MADS_PER_PRODUCT * (len(levs) - 1)
         if p + 1 < len(plan):
-            mads += 2 * MADS_PER_PRODUCT          # pass twiddle: table product + apply
+            # pass twiddle: read from the pass table (one product), or formed
+            # from the split tables (two products) above the table size limit
+            mads += MADS_PER_PRODUCT * (1 if l + sum(plan[p + 1:]) <= PASS_TABLE_MAX_LOG else 2)
         if p == 0 and kind == 2:
             mads += 2 * MADS_PER_PRODUCT          # coset pre-scale
         if p + 1 == len(plan) and kind == 1:
             mads += MADS_PER_PRODUCT              # N^-1
         if p + 1 == len(plan) and kind == 3:
             mads += 3 * MADS_PER_PRODUCT          # N^-1 g^-k
-        out.append({"levels": levs, "mads": mads, "mfma_ops": 2048 * sum(1 << m for m in levs)})
+        rest = sum(plan[p + 1:])
+        # HBM: read and write every element; a non-last pass also reads its
+        # twiddle table (one 32-byte entry per element) when the library keeps one
+        hbm = 64 + (32 if p + 1 < len(plan) and l + rest <= PASS_TABLE_MAX_LOG else 0)
+        out.append({"levels": levs, "mads": mads, "mfma_ops": 2048 * sum(1 << m for m in levs), "hbm_bytes": hbm})
     return out
 
 
@@ -300,7 +307,7 @@ def main():
     t = per_launch_ms * 1e-3
     mads = n * sum(w["mads"] for w in work) / launches
     ops = n * sum(w["mfma_ops"] for w in work) / launches
-    hbm = 2 * n * 32
+    hbm = n * sum(w["hbm_bytes"] for w in work) / launches
     achieved = mads / t / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(MAD_PEAK_TMADS, 2),
                 "unit": "Tmad/s", "frac": round(achieved / MAD_PEAK_TMADS, 4), "traffic": measured_traffic(),
