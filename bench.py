@@ -7,8 +7,8 @@ stream the kernels run on, inputs already resident in HBM. The headline
 butterfly form, the 2^24 coset round trip, the uneven batch and the oracle
 on host cores are reported beside it.
 
-Prints one JSON line (see the keys below). ``--gpus`` above 1 exits: this
-build runs on one GPU.
+Prints one JSON line (see the keys below). ``--gpus`` above 1 exits: frntt
+runs on one GPU.
 """
 from __future__ import annotations
 
@@ -242,7 +242,7 @@ def main():
     args = ap.parse_args()
     extra = set() if args.quick else {c.strip() for c in args.only.split(",") if c.strip()}
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        print("bench.py: frntt runs on one GPU; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
