@@ -131,3 +131,38 @@ def test_server_budget_and_errors(ctx):
             srv.release(123456)                       # unknown ticket
     finally:
         srv.close()
+
+
+def test_server_poisson_mix_at_scale(ctx):
+    """400 Poisson-paced requests, NTT/INTT/coset-NTT 40/40/20, sizes
+    2^14..2^18 (seed 15): every result bit-exact against the oracle, and a
+    seeded sample of 100 identical when the same transform runs alone."""
+    srv = fr.Server(ctx, 8 << 30, slots=4)          # all 400 results stay resident until fetched
+    try:
+        reqs = si.request_stream(15, 400, 14, 18, rate_per_s=3000.0)
+        tickets = []
+        t0 = time.perf_counter()
+        for r in reqs:
+            while time.perf_counter() - t0 < r["t_arrive_s"]:
+                pass
+            tickets.append(srv.submit(r["kind"], r["log_n"], 15))
+        srv.drain(300)
+        st = srv.stats()
+        _say(f"server at scale: {st}")
+        assert st["completed"] == len(reqs) and st["batches"] >= 1
+        sample = {si.draw_u64(15, (1 << 23) + 99, j) % len(reqs) for j in range(100)}
+        threads = cref.max_threads()
+        for i, (r, tk) in enumerate(zip(reqs, tickets)):
+            done, lat = srv.poll(tk)
+            assert done and lat > 0
+            got = fetch(srv, tk, r["log_n"])
+            x = si.polynomial(15, r["log_n"], stream=tk)
+            assert np.array_equal(got, cref.transform(x, r["log_n"], r["kind"], threads=threads)), (tk, r)
+            if i in sample:
+                t = torch.empty((1 << r["log_n"], 4), dtype=torch.int64, device="cuda:0")
+                ctx.generate(t.data_ptr(), 15, tk, 0, 1 << r["log_n"])
+                ctx.transform_checked(t.data_ptr(), r["log_n"], 1, r["kind"])
+                torch.cuda.synchronize()
+                assert np.array_equal(t.cpu().numpy().view(np.uint64).reshape(-1, 4), got), (tk, r)
+    finally:
+        srv.close()
