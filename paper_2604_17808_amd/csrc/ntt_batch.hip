@@ -7,7 +7,7 @@ namespace frntt {
 
 __global__ __launch_bounds__(kMfmaThreads) void ntt_batch_kernel(BatchParams B, DevTables T) {
   __shared__ u32x4 lds[2 << kMaxLogT];
-  __shared__ i32x4 lds_f[bat_lds_size<4>()];
+  __shared__ i32x4 lds_f[kPlanBatLds];
   // the item slot shares the constant-block area: it is written and read
   // only between passes, when no MFMA level uses that area
   int& item_sh = *reinterpret_cast<int*>(&lds_f[0]);

@@ -480,12 +480,12 @@ __device__ FRNTT_INLINE void mfma_level(u32x4* lds, i32x4* blk, const PassParams
 template <int M, int TPW>
 __device__ FRNTT_INLINE void mfma_level_any(u32x4* lds, i32x4* blk, const PassParams& P, const DevTables& T,
                                             const LevelGeom& g, int64_t wg) {
-  if (!g.last) mfma_level<M, TPW, 1>(lds, blk, P, T, g, true, wg);
-  else if (!P.is_last && P.pass_tw) mfma_level<M, TPW, 5>(lds, blk, P, T, g, true, wg);
-  else if (!P.is_last) mfma_level<M, TPW, 2>(lds, blk, P, T, g, true, wg);
-  else if (P.post == 1) mfma_level<M, TPW, 3>(lds, blk, P, T, g, true, wg);
-  else if (P.post == 2) mfma_level<M, TPW, 4>(lds, blk, P, T, g, true, wg);
-  else mfma_level<M, TPW, 0>(lds, blk, P, T, g, true, wg);
+  if (!g.last) mfma_level<M, TPW, 1>(lds, blk, P, T, g, false, wg);
+  else if (!P.is_last && P.pass_tw) mfma_level<M, TPW, 5>(lds, blk, P, T, g, false, wg);
+  else if (!P.is_last) mfma_level<M, TPW, 2>(lds, blk, P, T, g, false, wg);
+  else if (P.post == 1) mfma_level<M, TPW, 3>(lds, blk, P, T, g, false, wg);
+  else if (P.post == 2) mfma_level<M, TPW, 4>(lds, blk, P, T, g, false, wg);
+  else mfma_level<M, TPW, 0>(lds, blk, P, T, g, false, wg);
 }
 
 // Level shapes: 2^(log_t - m - 5) tiles of 32 vectors, TPW = tiles / 8 per
@@ -509,6 +509,27 @@ __device__ FRNTT_INLINE void run_mfma_level(u32x4* lds, i32x4* lds_f, const Pass
   }
 }
 
+// Constant blocks and seeds of the (at most two) distinct level radices of a
+// pass, staged once per pass: the first level's radix at 0, the other one
+// after it. Runs before the tile's loads so that both overlap.
+__device__ FRNTT_INLINE int pass_bat_offset(const PassParams& P, int m) {
+  return m == P.lev_log[0] ? 0 : (1 << P.lev_log[0]) * 72;
+}
+
+template <int NT>
+__device__ FRNTT_INLINE void stage_pass_bats(i32x4* lds_f, const PassParams& P, const DevTables& T) {
+  for (int lev = 0; lev < P.nlev; ++lev) {
+    const int m = P.lev_log[lev];
+    if (lev > 0 && (m == P.lev_log[0] || m == P.lev_log[lev - 1])) continue;
+    const int rho = 1 << m;
+    i32x4* dst = lds_f + pass_bat_offset(P, m);
+    const i32x4* bat = T.bat[P.dir][m];
+    const i32x4* seeds = T.bat_init[P.dir][m];
+    for (int i = threadIdx.x; i < rho * 64; i += NT) dst[i] = bat[i];
+    for (int i = threadIdx.x; i < rho * 8; i += NT) dst[rho * 64 + i] = seeds[i];
+  }
+}
+
 __device__ FRNTT_INLINE void mfma_levels(u32x4* lds, i32x4* lds_f, const PassParams& P, const DevTables& T,
                                          int64_t wg) {
   int pprev = 0;
@@ -521,12 +542,10 @@ __device__ FRNTT_INLINE void mfma_levels(u32x4* lds, i32x4* lds_f, const PassPar
     g.q_log = rest;
     g.next_m = lev + 1 < P.nlev ? P.lev_log[lev + 1] : 0;
     g.last = lev + 1 == P.nlev;
-    run_mfma_level(lds, lds_f, P, T, g, wg);
+    run_mfma_level(lds, lds_f + pass_bat_offset(P, g.m), P, T, g, wg);
     pprev += g.m;
   }
 }
-
-// ------------------------------------------------------------- one pass
 
 // A pass whose levels are known at compile time (radices 2^M0, 2^M1 and,
 // if M2 > 0, 2^M2, staged tile of 4096 elements): the constant blocks of
@@ -596,9 +615,10 @@ template <int ENGINE, int NT>
 __device__ FRNTT_INLINE void run_pass(u32x4* lds, i32x4* lds_f, const PassParams& P, const DevTables& T,
                                       int64_t wg) {
   static_assert(ENGINE == 0 || NT == kMfmaThreads, "MFMA levels assume kMfmaThreads");
+  const bool use_mfma = ENGINE == 1 || (ENGINE == 2 && P.engine == 1);
+  if (use_mfma) stage_pass_bats<NT>(lds_f, P, T);
   load_lines<NT>(lds, P, T, wg);
   __syncthreads();
-  const bool use_mfma = ENGINE == 1 || (ENGINE == 2 && P.engine == 1);
   if (use_mfma) mfma_levels(lds, lds_f, P, T, wg);
   else bfly_stages<NT>(lds, P, T);
   store_lines<NT>(lds, P, T, wg, !use_mfma);

@@ -7,7 +7,7 @@ namespace frntt {
 
 __global__ __launch_bounds__(kMfmaThreads) void ntt_pass_mfma_kernel(PassParams P, DevTables T) {
   __shared__ u32x4 lds[2 << kMaxLogT];
-  __shared__ i32x4 lds_f[bat_lds_size<4>()];
+  __shared__ i32x4 lds_f[kPlanBatLds];
   run_pass<1, kMfmaThreads>(lds, lds_f, P, T, logical_wg(P));
 }
 
