@@ -1,0 +1,49 @@
+"""The bench's algorithmic work model (roofline numerators): level splits,
+multiply-add, MFMA-operation and HBM-byte counts per pass, and the guard that
+drops measured traffic once the kernel sources differ from the profiled ones."""
+from __future__ import annotations
+
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_level_split_matches_the_library_rule():
+    # fewest levels of radix <= 16, larger levels first
+    assert bench.level_split(12) == [4, 4, 4]
+    assert bench.level_split(11) == [4, 4, 3]
+    assert bench.level_split(10) == [4, 3, 3]
+    assert bench.level_split(9) == [3, 3, 3]
+    assert bench.level_split(8) == [4, 4]
+    assert bench.level_split(5) == [3, 2]
+    assert bench.level_split(4) == [4]
+
+
+def test_work_per_element_2e20_forward():
+    w = bench.algorithmic_work([10, 10], kind=0)
+    # pass 0: 3 merges + 2 level twiddles + pass twiddle from the table
+    assert w[0]["mads"] == 3 * 20 + 3 * 162 and w[0]["hbm_bytes"] == 96
+    # pass 1 (last, forward): 3 merges + 2 level twiddles, no epilogue
+    assert w[1]["mads"] == 3 * 20 + 2 * 162 and w[1]["hbm_bytes"] == 64
+    assert all(p["mfma_ops"] == 2048 * (16 + 8 + 8) for p in w)
+
+
+def test_work_epilogues_and_large_passes():
+    inv = bench.algorithmic_work([12, 12], kind=1)
+    assert inv[1]["mads"] == 3 * 20 + 2 * 162 + 162          # N^-1
+    cinv = bench.algorithmic_work([12, 12], kind=3)
+    assert cinv[1]["mads"] == 3 * 20 + 2 * 162 + 3 * 162     # N^-1 g^-k
+    coset = bench.algorithmic_work([12, 12], kind=2)
+    assert coset[0]["mads"] == 3 * 20 + 3 * 162 + 2 * 162    # + coset pre-scale
+    # above the table limit the pass twiddle takes two products and no table read
+    big = bench.algorithmic_work([10, 9, 9], kind=0)
+    assert big[0]["mads"] == 3 * 20 + 2 * 162 + 2 * 162 and big[0]["hbm_bytes"] == 64
+
+
+def test_traffic_only_for_the_profiled_sources(monkeypatch):
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "not-the-profiled-sources")
+    assert bench.measured_traffic() is None
