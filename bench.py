@@ -5,7 +5,9 @@ A step is one forward NTT of N = 2^20 seeded uniform field elements (the
 stream the kernels run on, inputs already resident in HBM. The headline
 ``value`` is the int8-MFMA limb-matmul form in Melem/s (= N / time); the
 butterfly form, the 2^24 coset round trip, the uneven batch and the oracle
-on host cores are reported beside it.
+on host cores are reported beside it. Before any timed region both forms run
+alternately, untimed, for ``--settle-s`` seconds so that neither is timed
+while the GPU clock is still ramping up from idle.
 
 Prints one JSON line (see the keys below). ``--gpus`` above 1 exits: frntt
 runs on one GPU.
@@ -53,6 +55,20 @@ def time_transform(ctx, torch, ptr, log_n, batch, kind, algo, steps, warmup, str
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps
+
+
+def settle_clocks(ctx, torch, fr, ptr, log_n, stream, seconds):
+    """Untimed: alternate both forms' transforms for `seconds` of wall time so
+    that the GPU clock has left its idle state before anything is timed.
+    Without it the form timed first runs partly at a lower clock."""
+    if seconds <= 0:
+        return
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for algo in (fr.ALGO_FOURSTEP_MFMA, fr.ALGO_BUTTERFLY):
+            for _ in range(100):
+                ctx.transform_checked(ptr, log_n, 1, fr.FWD, stream, algo)
+        torch.cuda.synchronize()
 
 
 def level_split(l, max_m=4):
@@ -229,7 +245,7 @@ def bench_c5(ctx, fr, n_requests):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing on host cores")
     ap.add_argument("--quick", action="store_true", help="headline config only")
@@ -239,6 +255,8 @@ def main():
     ap.add_argument("--calib", action="store_true",
                     help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
     ap.add_argument("--serve-requests", type=int, default=10000)
+    ap.add_argument("--settle-s", type=float, default=1.0,
+                    help="untimed seconds of alternating transforms before the first timed region")
     args = ap.parse_args()
     extra = set() if args.quick else {c.strip() for c in args.only.split(",") if c.strip()}
     if args.gpus != 1:
@@ -268,6 +286,8 @@ def main():
     n = 1 << log_n
     buf = torch.empty((n, 4), dtype=torch.int64, device="cuda:0")
     ctx.generate(buf.data_ptr(), 2, 0, 0, n, stream)
+    log(f"settling clocks for {args.settle_s} s")
+    settle_clocks(ctx, torch, fr, buf.data_ptr(), log_n, stream, args.settle_s)
     res = {}
     for name, algo in (("mfma", fr.ALGO_FOURSTEP_MFMA), ("butterfly", fr.ALGO_BUTTERFLY)):
         log(f"timing 2^20 forward {name}")
@@ -327,6 +347,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "settle_s": args.settle_s,
         "ms_per_step": round(mf["ms"], 5),
         "higher_is_better": True,
         "scaling": "weak",
