@@ -93,10 +93,13 @@ def algorithmic_work(plan, kind=0):
             mads += MADS_PER_PRODUCT * (1 if l + sum(plan[p + 1:]) <= PASS_TABLE_MAX_LOG else 2)
         if p == 0 and kind == 2:
             mads += 2 * MADS_PER_PRODUCT          # coset pre-scale
-        if p + 1 == len(plan) and kind == 1:
+        # an inverse transform takes N^-1 from the first pass's table when
+        # that pass keeps one; otherwise the last pass multiplies by it
+        folded = len(plan) > 1 and sum(plan) <= PASS_TABLE_MAX_LOG
+        if p + 1 == len(plan) and kind == 1 and not folded:
             mads += MADS_PER_PRODUCT              # N^-1
         if p + 1 == len(plan) and kind == 3:
-            mads += 3 * MADS_PER_PRODUCT          # N^-1 g^-k
+            mads += (2 if folded else 3) * MADS_PER_PRODUCT   # g^-k (N^-1 g^-k)
         rest = sum(plan[p + 1:])
         # HBM: read and write every element; a non-last pass also reads its
         # twiddle table (one 32-byte entry per element) when the library keeps one

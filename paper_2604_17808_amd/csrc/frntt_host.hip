@@ -157,6 +157,9 @@ int build_passes(frntt_ctx* ctx, const Plan& plan_in, int log_n, int batch, int 
   Plan plan = plan_in;
   out->clear();
   const int dir = (kind == FRNTT_INV || kind == FRNTT_COSET_INV) ? 1 : 0;
+  // an inverse transform whose first pass reads a twiddle table takes N^-1
+  // from that table, and its last pass skips the N^-1 product
+  const bool fold = dir == 1 && first_pass_scaled(plan);
   int d = 0;
   for (int p = 0; p < plan.n_pass; ++p) {
     const int l = plan.pass_log[p];
@@ -184,15 +187,15 @@ int build_passes(frntt_ctx* ctx, const Plan& plan_in, int log_n, int batch, int 
     P.dir = dir;
     P.coset_pre = (first && kind == FRNTT_COSET) ? 1 : 0;
     P.post = 0;
-    if (last && kind == FRNTT_INV) P.post = 1;
-    if (last && kind == FRNTT_COSET_INV) P.post = 2;
+    if (last && kind == FRNTT_INV) P.post = fold ? 0 : 1;
+    if (last && kind == FRNTT_COSET_INV) P.post = fold ? 3 : 2;
     const int64_t lines = ((int64_t)batch << log_n) >> l;
     P.wg_count = lines >> lg;
     P.xcd_remap = 1;
     P.pass_tw = nullptr;
     if (!last) {
       int rc = FRNTT_OK;
-      P.pass_tw = pass_table(ctx, dir, l, s, &rc);
+      P.pass_tw = pass_table(ctx, dir, l, s, first && fold ? log_n : -1, &rc);
       if (rc != FRNTT_OK) return rc;
     }
     out->push_back(P);
@@ -201,10 +204,21 @@ int build_passes(frntt_ctx* ctx, const Plan& plan_in, int log_n, int batch, int 
   return FRNTT_OK;
 }
 
-const u32x4* pass_table(frntt_ctx* ctx, int dir, int log_r, int log_s, int* rc) {
+bool first_pass_scaled(const Plan& plan) {
+  if (plan.n_pass < 2) return false;
+  int log_n = 0;
+  for (int p = 0; p < plan.n_pass; ++p) log_n += plan.pass_log[p];
+  return log_n <= kPassTableMaxLog;
+}
+
+static int pass_table_key(int dir, int log_r, int log_s, int scale_log) {
+  return ((scale_log + 1) << 20) | (dir << 16) | (log_r << 8) | log_s;
+}
+
+const u32x4* pass_table(frntt_ctx* ctx, int dir, int log_r, int log_s, int scale_log, int* rc) {
   *rc = FRNTT_OK;
   if (log_r + log_s > kPassTableMaxLog) return nullptr;
-  const int key = (dir << 16) | (log_r << 8) | log_s;
+  const int key = pass_table_key(dir, log_r, log_s, scale_log);
   std::lock_guard<std::mutex> lk(ctx->tw_mu);
   auto it = ctx->pass_tw.find(key);
   if (it != ctx->pass_tw.end()) return (const u32x4*)it->second;
@@ -223,7 +237,7 @@ const u32x4* pass_table(frntt_ctx* ctx, int dir, int log_r, int log_s, int* rc) 
     const int64_t n = 1ll << (log_r + log_s);
     const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
     hipLaunchKernelGGL(pass_twiddle_kernel, dim3(grid), dim3(256), 0, st, (u32x4*)p, ctx->tables, dir, log_r,
-                       log_s);
+                       log_s, scale_log);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     hipStreamDestroy(st);
@@ -240,6 +254,7 @@ const u32x4* pass_table(frntt_ctx* ctx, int dir, int log_r, int log_s, int* rc) 
 
 size_t pending_pass_table_bytes(frntt_ctx* ctx, const Plan& plan, int kind) {
   const int dir = (kind == FRNTT_INV || kind == FRNTT_COSET_INV) ? 1 : 0;
+  const bool fold = dir == 1 && first_pass_scaled(plan);
   size_t bytes = 0;
   std::lock_guard<std::mutex> lk(ctx->tw_mu);
   for (int p = 0; p + 1 < plan.n_pass; ++p) {
@@ -247,7 +262,8 @@ size_t pending_pass_table_bytes(frntt_ctx* ctx, const Plan& plan, int kind) {
     for (int q = p + 1; q < plan.n_pass; ++q) s += plan.pass_log[q];
     const int l = plan.pass_log[p];
     if (l + s > kPassTableMaxLog) continue;
-    if (!ctx->pass_tw.count((dir << 16) | (l << 8) | s)) bytes += (size_t)32 << (l + s);
+    const int scale_log = p == 0 && fold ? l + s : -1;
+    if (!ctx->pass_tw.count(pass_table_key(dir, l, s, scale_log))) bytes += (size_t)32 << (l + s);
   }
   return bytes;
 }

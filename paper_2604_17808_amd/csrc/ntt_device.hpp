@@ -58,7 +58,8 @@ struct PassParams {
   int engine;       // 0: butterfly stages, 1: MFMA levels (lev_log)
   int dir;          // 0: forward roots, 1: inverse roots
   int coset_pre;    // first pass of a coset transform: x_n *= g^n on load
-  int post;         // last pass: 0 none, 1 scale by N^-1, 2 scale by N^-1 g^-k
+  int post;         // last pass: 0 none, 1 scale by N^-1, 2 scale by N^-1 g^-k, 3 scale by g^-k
+                   // (2^-log_n then rides in the first pass's twiddle table)
   int xcd_remap;    // map consecutive logical workgroups onto one XCD
   const u32x4* pass_tw;  // non-last pass: table of its twiddles at [k][rest], or nullptr
 };

@@ -110,6 +110,9 @@ __device__ FRNTT_INLINE void store_lines(const u32x4* lds, const PassParams& P, 
     } else if (P.post == 2) {
       const uint32_t idx = (uint32_t)(mp.poly_off + ((int64_t)k << mp.out_shift));
       y = mont_mul(mont_mul(ld_elem(T.ninv, P.log_n), coset_pow(T, 1, idx)), y);
+    } else if (P.post == 3) {
+      const uint32_t idx = (uint32_t)(mp.poly_off + ((int64_t)k << mp.out_shift));
+      y = mont_mul(coset_pow(T, 1, idx), y);
     }
     st_elem(P.dst, mp.out_base + ((int64_t)k << mp.out_shift), y);
   }
@@ -298,7 +301,7 @@ constexpr int bat_lds_size() { return (1 << M) * 72; }  // i32x4 units
 //           Montgomery product).
 template <int KIND>
 struct PairWork {
-  static constexpr int kProducts = KIND == 0 ? 0 : KIND == 2 ? 2 : KIND == 4 ? 3 : 1;
+  static constexpr int kProducts = KIND == 0 ? 0 : (KIND == 2 || KIND == 6) ? 2 : KIND == 4 ? 3 : 1;
   static constexpr int kSteps = kMergeSteps + 11 * kProducts;
   Merge mg;
   MontMul mm;
@@ -320,7 +323,7 @@ struct PairWork {
       if constexpr (S == P0 - 1) y = mg.result();
     } else if constexpr (KIND == 1 || KIND == 3 || KIND == 5) {
       prod<S - P0>(tw, y, y);
-    } else if constexpr (KIND == 2) {
+    } else if constexpr (KIND == 2 || KIND == 6) {
       if constexpr (S < P1) prod<S - P0>(tw, tw2, tw);
       else prod<S - P1>(tw, y, y);
     } else {
@@ -396,7 +399,7 @@ struct TileLoop {
       // KIND 2, 5: the line's pass-twiddle row; KIND 4: the line's output base
       // and stride inside its polynomial
       LineMap mp{};
-      if (KIND == 2 || KIND == 4 || KIND == 5) mp = map_line(P, wg * (1 << P.log_g) + (v & ((1 << P.log_g) - 1)));
+      if (KIND == 2 || KIND == 4 || KIND == 5 || KIND == 6) mp = map_line(P, wg * (1 << P.log_g) + (v & ((1 << P.log_g) - 1)));
       const int64_t rest = mp.rest;
 #pragma unroll 1
       for (int kp = 0; kp < NKP; ++kp) {
@@ -412,11 +415,11 @@ struct TileLoop {
         }
         if (KIND == 5) wk.tw = ld_elem(P.pass_tw, ((int64_t)(kk + (k << g.pprev_log)) << P.log_s) + rest);
         if (KIND == 3) wk.tw = ld_elem(Tb.ninv, P.log_n);
-        if (KIND == 4) {
+        if (KIND == 4 || KIND == 6) {
           const uint32_t idx = (uint32_t)(mp.poly_off + ((int64_t)(kk + (k << g.pprev_log)) << mp.out_shift));
           wk.tw = ld_elem(Tb.g_lo[1], idx & ((1u << kSplit) - 1));
           wk.tw2 = ld_elem(Tb.g_hi[1], idx >> kSplit);
-          wk.tw3 = ld_elem(Tb.ninv, P.log_n);
+          if (KIND == 4) wk.tw3 = ld_elem(Tb.ninv, P.log_n);
         }
         if (kp + 1 < NKP) {
           mfma_pair_work<RHO, true>(lds_f, init, B[T], 2 * kp + 2, lane, half, n0, n1, wk);
@@ -485,6 +488,7 @@ __device__ FRNTT_INLINE void mfma_level_any(u32x4* lds, i32x4* blk, const PassPa
   else if (!P.is_last) mfma_level<M, TPW, 2>(lds, blk, P, T, g, false, wg);
   else if (P.post == 1) mfma_level<M, TPW, 3>(lds, blk, P, T, g, false, wg);
   else if (P.post == 2) mfma_level<M, TPW, 4>(lds, blk, P, T, g, false, wg);
+  else if (P.post == 3) mfma_level<M, TPW, 6>(lds, blk, P, T, g, false, wg);
   else mfma_level<M, TPW, 0>(lds, blk, P, T, g, false, wg);
 }
 
@@ -586,6 +590,7 @@ __device__ FRNTT_INLINE void plan_last_level(u32x4* lds, i32x4* blk, const PassP
   else if (!P.is_last) mfma_level<M, TPW, 2>(lds, blk, P, T, g, false, wg);
   else if (P.post == 1) mfma_level<M, TPW, 3>(lds, blk, P, T, g, false, wg);
   else if (P.post == 2) mfma_level<M, TPW, 4>(lds, blk, P, T, g, false, wg);
+  else if (P.post == 3) mfma_level<M, TPW, 6>(lds, blk, P, T, g, false, wg);
   else mfma_level<M, TPW, 0>(lds, blk, P, T, g, false, wg);
 }
 

@@ -69,13 +69,19 @@ __global__ void zero_words_kernel(unsigned int* p, int64_t n) {
 
 // Twiddles of a non-last pass, w_(2^(log_r + log_s))^(rest * k) in
 // Montgomery form, at index k * 2^log_s + rest (k < 2^log_r, rest < 2^log_s):
-// the stores of a pass then read them contiguously along its lines.
-__global__ void pass_twiddle_kernel(u32x4* dst, DevTables T, int dir, int log_r, int log_s) {
+// the stores of a pass then read them contiguously along its lines. With
+// scale_log >= 0 every entry also carries the factor 2^-scale_log: the N^-1
+// of an inverse transform is one constant factor on every output, so the
+// first pass can apply it with its twiddle instead of the last pass spending
+// a product on it.
+__global__ void pass_twiddle_kernel(u32x4* dst, DevTables T, int dir, int log_r, int log_s, int scale_log) {
   const int64_t n = 1ll << (log_r + log_s);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const uint64_t k = (uint64_t)i >> log_s;
     const uint64_t rest = (uint64_t)i & ((1ull << log_s) - 1);
-    st_elem(dst, i, pow_tw(T, dir, log_r + log_s, rest * k));
+    fr_t w = pow_tw(T, dir, log_r + log_s, rest * k);
+    if (scale_log >= 0) w = mont_mul(ld_elem(T.ninv, scale_log), w);
+    st_elem(dst, i, w);
   }
 }
 

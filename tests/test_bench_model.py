@@ -33,10 +33,15 @@ def test_work_per_element_2e20_forward():
 
 
 def test_work_epilogues_and_large_passes():
+    # N^-1 rides in the first pass's twiddle table: no product in the last pass
     inv = bench.algorithmic_work([12, 12], kind=1)
-    assert inv[1]["mads"] == 3 * 20 + 2 * 162 + 162          # N^-1
+    assert inv[1]["mads"] == 3 * 20 + 2 * 162
     cinv = bench.algorithmic_work([12, 12], kind=3)
-    assert cinv[1]["mads"] == 3 * 20 + 2 * 162 + 3 * 162     # N^-1 g^-k
+    assert cinv[1]["mads"] == 3 * 20 + 2 * 162 + 2 * 162     # g^-k
+    # a single pass (no table) and a plan above the table limit keep it
+    assert bench.algorithmic_work([12], kind=1)[0]["mads"] == 3 * 20 + 2 * 162 + 162
+    assert bench.algorithmic_work([12], kind=3)[0]["mads"] == 3 * 20 + 2 * 162 + 3 * 162
+    assert bench.algorithmic_work([9, 9, 8], kind=1)[2]["mads"] == 2 * 20 + 162 + 162
     coset = bench.algorithmic_work([12, 12], kind=2)
     assert coset[0]["mads"] == 3 * 20 + 3 * 162 + 2 * 162    # + coset pre-scale
     # above the table limit the pass twiddle takes two products and no table read
