@@ -160,8 +160,11 @@ size_t frntt_scratch_bytes(int log_n, int batch);
  * (the twiddle table of every pass but the last, w^(rest*k) of the pass's
  * sub-problem: the pass twiddles of the 3-step / 5-step decomposition, Eq. 1,
  * which the paper generates offline), so that later calls allocate nothing
- * for them. Otherwise they are built on first use. Synchronous. Errors:
- * EINVAL, ERANGE, ENOMEM, EHIP. */
+ * for them. Otherwise they are built on first use. The first pass of an
+ * inverse kind reads a table whose entries also carry N^-1 (its last pass then
+ * skips that product), so forward and inverse kinds of one size use distinct
+ * tables, while a coset kind shares the table of the plain kind of its
+ * direction. Synchronous. Errors: EINVAL, ERANGE, ENOMEM, EHIP. */
 int frntt_prepare(frntt_ctx *ctx, int log_n, int kind);
 
 /* Device bytes held by the context's tables, including the pass-twiddle
