@@ -5,6 +5,36 @@
 
 namespace frntt {
 
+// One (pass, workgroup) item. A matrix-form pass with a full 4096-element
+// tile runs the level code specialised to its level split (the same bodies
+// as the plan kernels of single transforms); other passes take the generic
+// per-pass path.
+static_assert(PassPlan<4, 4, 4>::kLds <= kPlanBatLds && PassPlan<4, 4, 3>::kLds <= kPlanBatLds &&
+                  PassPlan<4, 3, 3>::kLds <= kPlanBatLds && PassPlan<3, 3, 3>::kLds <= kPlanBatLds &&
+                  PassPlan<4, 4, 0>::kLds <= kPlanBatLds && PassPlan<4, 3, 0>::kLds <= kPlanBatLds &&
+                  PassPlan<3, 3, 0>::kLds <= kPlanBatLds && PassPlan<3, 2, 0>::kLds <= kPlanBatLds,
+              "the batch kernel's constant-block area holds every plan's blocks");
+
+__device__ FRNTT_INLINE void run_batch_pass(u32x4* lds, i32x4* lds_f, const PassParams& P, const DevTables& T,
+                                            int64_t wg) {
+  const int nlev = P.nlev;
+  const int code = __builtin_amdgcn_readfirstlane(
+      P.engine == 1 && P.log_t == kMaxLogT
+          ? nlev * 1000 + P.lev_log[0] * 100 + (nlev > 1 ? P.lev_log[1] : 0) * 10 + (nlev > 2 ? P.lev_log[2] : 0)
+          : 0);
+  switch (code) {
+    case 3444: run_pass_plan<4, 4, 4>(lds, lds_f, P, T, wg); return;
+    case 3443: run_pass_plan<4, 4, 3>(lds, lds_f, P, T, wg); return;
+    case 3433: run_pass_plan<4, 3, 3>(lds, lds_f, P, T, wg); return;
+    case 3333: run_pass_plan<3, 3, 3>(lds, lds_f, P, T, wg); return;
+    case 2440: run_pass_plan<4, 4, 0>(lds, lds_f, P, T, wg); return;
+    case 2430: run_pass_plan<4, 3, 0>(lds, lds_f, P, T, wg); return;
+    case 2330: run_pass_plan<3, 3, 0>(lds, lds_f, P, T, wg); return;
+    case 2320: run_pass_plan<3, 2, 0>(lds, lds_f, P, T, wg); return;
+    default: run_pass<2, kMfmaThreads>(lds, lds_f, P, T, wg);
+  }
+}
+
 __global__ __launch_bounds__(kMfmaThreads) void ntt_batch_kernel(BatchParams B, DevTables T) {
   __shared__ u32x4 lds[2 << kMaxLogT];
   __shared__ i32x4 lds_f[kPlanBatLds];
@@ -45,7 +75,7 @@ __global__ __launch_bounds__(kMfmaThreads) void ntt_batch_kernel(BatchParams B, 
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const PassParams& P = B.passes[p];
     const int64_t wg = B.item_wg[item];
-    run_pass<2, kMfmaThreads>(lds, lds_f, P, T, wg);
+    run_batch_pass(lds, lds_f, P, T, wg);
     __syncthreads();
     if (wave == 0) {
       __threadfence();
