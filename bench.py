@@ -84,6 +84,10 @@ def algorithmic_work(plan, kind=0):
     """Per-element multiply-adds and int8 MFMA operations of each pass of a
     transform (forward: kind 0) with HBM passes `plan`."""
     out = []
+    # the first pass keeps a twiddle table: an inverse transform takes N^-1
+    # from it (otherwise the last pass multiplies by it), a coset transform
+    # the per-line part of its pre-scale
+    folded = len(plan) > 1 and sum(plan) <= PASS_TABLE_MAX_LOG
     for p, l in enumerate(plan):
         levs = level_split(l)
         mads = MADS_PER_MERGE * len(levs) + MADS_PER_PRODUCT * (len(levs) - 1)
@@ -92,10 +96,9 @@ def algorithmic_work(plan, kind=0):
             # from the split tables (two products) above the table size limit
             mads += MADS_PER_PRODUCT * (1 if l + sum(plan[p + 1:]) <= PASS_TABLE_MAX_LOG else 2)
         if p == 0 and kind == 2:
-            mads += 2 * MADS_PER_PRODUCT          # coset pre-scale
-        # an inverse transform takes N^-1 from the first pass's table when
-        # that pass keeps one; otherwise the last pass multiplies by it
-        folded = len(plan) > 1 and sum(plan) <= PASS_TABLE_MAX_LOG
+            # coset pre-scale: one product when the first pass's table carries
+            # the per-line factor (and holds the per-element one), else two
+            mads += (1 if folded else 2) * MADS_PER_PRODUCT
         if p + 1 == len(plan) and kind == 1 and not folded:
             mads += MADS_PER_PRODUCT              # N^-1
         if p + 1 == len(plan) and kind == 3:

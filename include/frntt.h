@@ -162,9 +162,11 @@ size_t frntt_scratch_bytes(int log_n, int batch);
  * which the paper generates offline), so that later calls allocate nothing
  * for them. Otherwise they are built on first use. The first pass of an
  * inverse kind reads a table whose entries also carry N^-1 (its last pass then
- * skips that product), so forward and inverse kinds of one size use distinct
- * tables, while a coset kind shares the table of the plain kind of its
- * direction. Synchronous. Errors: EINVAL, ERANGE, ENOMEM, EHIP. */
+ * skips that product); that of a forward coset kind carries the per-line part
+ * g^rest of the coset factor and ends with 2^l entries of its per-element part
+ * for the pre-scale. So FWD, COSET and INV of one size use three distinct
+ * tables, and COSET_INV shares the INV table. Synchronous. Errors: EINVAL,
+ * ERANGE, ENOMEM, EHIP. */
 int frntt_prepare(frntt_ctx *ctx, int log_n, int kind);
 
 /* Device bytes held by the context's tables, including the pass-twiddle

@@ -160,6 +160,9 @@ int build_passes(frntt_ctx* ctx, const Plan& plan_in, int log_n, int batch, int 
   // an inverse transform whose first pass reads a twiddle table takes N^-1
   // from that table, and its last pass skips the N^-1 product
   const bool fold = dir == 1 && first_pass_scaled(plan);
+  // a coset transform whose first pass reads a twiddle table takes the
+  // per-line part of g^n from that table and the rest from its tail
+  const bool coset_fold = kind == FRNTT_COSET && first_pass_scaled(plan);
   int d = 0;
   for (int p = 0; p < plan.n_pass; ++p) {
     const int l = plan.pass_log[p];
@@ -185,7 +188,7 @@ int build_passes(frntt_ctx* ctx, const Plan& plan_in, int log_n, int batch, int 
     for (int i = 0; i < kMaxLevels; ++i) P.lev_log[i] = plan.lev_log[p][i];
     P.engine = (algo == FRNTT_ALGO_FOURSTEP_MFMA && mfma_ok) ? 1 : 0;
     P.dir = dir;
-    P.coset_pre = (first && kind == FRNTT_COSET) ? 1 : 0;
+    P.coset_pre = (first && kind == FRNTT_COSET) ? (coset_fold ? 2 : 1) : 0;
     P.post = 0;
     if (last && kind == FRNTT_INV) P.post = fold ? 0 : 1;
     if (last && kind == FRNTT_COSET_INV) P.post = fold ? 3 : 2;
@@ -195,7 +198,7 @@ int build_passes(frntt_ctx* ctx, const Plan& plan_in, int log_n, int batch, int 
     P.pass_tw = nullptr;
     if (!last) {
       int rc = FRNTT_OK;
-      P.pass_tw = pass_table(ctx, dir, l, s, first && fold ? log_n : -1, &rc);
+      P.pass_tw = pass_table(ctx, dir, l, s, first && fold ? log_n : -1, first && coset_fold ? 1 : 0, &rc);
       if (rc != FRNTT_OK) return rc;
     }
     out->push_back(P);
@@ -211,18 +214,22 @@ bool first_pass_scaled(const Plan& plan) {
   return log_n <= kPassTableMaxLog;
 }
 
-static int pass_table_key(int dir, int log_r, int log_s, int scale_log) {
-  return ((scale_log + 1) << 20) | (dir << 16) | (log_r << 8) | log_s;
+static int pass_table_key(int dir, int log_r, int log_s, int scale_log, int coset) {
+  return (coset << 26) | ((scale_log + 1) << 20) | (dir << 16) | (log_r << 8) | log_s;
 }
 
-const u32x4* pass_table(frntt_ctx* ctx, int dir, int log_r, int log_s, int scale_log, int* rc) {
+static size_t pass_table_entries(int log_r, int log_s, int coset) {
+  return ((size_t)1 << (log_r + log_s)) + (coset ? ((size_t)1 << log_r) : 0);
+}
+
+const u32x4* pass_table(frntt_ctx* ctx, int dir, int log_r, int log_s, int scale_log, int coset, int* rc) {
   *rc = FRNTT_OK;
   if (log_r + log_s > kPassTableMaxLog) return nullptr;
-  const int key = pass_table_key(dir, log_r, log_s, scale_log);
+  const int key = pass_table_key(dir, log_r, log_s, scale_log, coset);
   std::lock_guard<std::mutex> lk(ctx->tw_mu);
   auto it = ctx->pass_tw.find(key);
   if (it != ctx->pass_tw.end()) return (const u32x4*)it->second;
-  const size_t bytes = (size_t)32 << (log_r + log_s);
+  const size_t bytes = 32 * pass_table_entries(log_r, log_s, coset);
   void* p = nullptr;
   hipError_t e = hipMalloc(&p, bytes);
   if (e != hipSuccess) {
@@ -234,10 +241,10 @@ const u32x4* pass_table(frntt_ctx* ctx, int dir, int log_r, int log_s, int scale
   hipStream_t st = nullptr;
   e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
   if (e == hipSuccess) {
-    const int64_t n = 1ll << (log_r + log_s);
+    const int64_t n = (int64_t)pass_table_entries(log_r, log_s, coset);
     const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
     hipLaunchKernelGGL(pass_twiddle_kernel, dim3(grid), dim3(256), 0, st, (u32x4*)p, ctx->tables, dir, log_r,
-                       log_s, scale_log);
+                       log_s, scale_log, coset);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     hipStreamDestroy(st);
@@ -255,6 +262,7 @@ const u32x4* pass_table(frntt_ctx* ctx, int dir, int log_r, int log_s, int scale
 size_t pending_pass_table_bytes(frntt_ctx* ctx, const Plan& plan, int kind) {
   const int dir = (kind == FRNTT_INV || kind == FRNTT_COSET_INV) ? 1 : 0;
   const bool fold = dir == 1 && first_pass_scaled(plan);
+  const bool coset_fold = kind == FRNTT_COSET && first_pass_scaled(plan);
   size_t bytes = 0;
   std::lock_guard<std::mutex> lk(ctx->tw_mu);
   for (int p = 0; p + 1 < plan.n_pass; ++p) {
@@ -263,7 +271,9 @@ size_t pending_pass_table_bytes(frntt_ctx* ctx, const Plan& plan, int kind) {
     const int l = plan.pass_log[p];
     if (l + s > kPassTableMaxLog) continue;
     const int scale_log = p == 0 && fold ? l + s : -1;
-    if (!ctx->pass_tw.count(pass_table_key(dir, l, s, scale_log))) bytes += (size_t)32 << (l + s);
+    const int coset = p == 0 && coset_fold ? 1 : 0;
+    if (!ctx->pass_tw.count(pass_table_key(dir, l, s, scale_log, coset)))
+      bytes += 32 * pass_table_entries(l, s, coset);
   }
   return bytes;
 }

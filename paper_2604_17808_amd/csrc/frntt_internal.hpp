@@ -21,7 +21,8 @@ __global__ void generate_kernel(u32x4* out, uint64_t seed, uint64_t stream_id, u
                                 uint64_t count);
 __global__ void validate_kernel(const u32x4* data, uint64_t count, unsigned int* flag);
 __global__ void zero_words_kernel(unsigned int* p, int64_t n);
-__global__ void pass_twiddle_kernel(u32x4* dst, DevTables T, int dir, int log_r, int log_s, int scale_log);
+__global__ void pass_twiddle_kernel(u32x4* dst, DevTables T, int dir, int log_r, int log_s, int scale_log,
+                                    int coset);
 
 // Decomposition of one transform size into passes and levels.
 struct Plan {
@@ -97,12 +98,14 @@ Plan plan_for(const frntt_ctx* ctx, int algo, int log_n);
 int build_passes(frntt_ctx* ctx, const Plan& plan, int log_n, int batch, int kind,
                  void* data, void* scratch, std::vector<PassParams>* out, int algo);
 // Pass-twiddle table w_(2^(log_r + log_s))^(rest * k) at [k][rest] for a
-// non-last pass, times 2^-scale_log when scale_log >= 0 (built and cached per
-// (dir, log_r, log_s, scale_log) on first use), or nullptr when it would
+// non-last pass, times 2^-scale_log when scale_log >= 0, times g^rest with
+// 2^log_r pre-scale entries (g^(2^log_s))^j appended when coset != 0 (built
+// and cached per (dir, log_r, log_s, scale_log, coset) on first use), or
+// nullptr when it would
 // exceed kPassTableMaxLog entries (the pass then forms each twiddle from the
 // split tables).
 constexpr int kPassTableMaxLog = 25;
-const u32x4* pass_table(frntt_ctx* ctx, int dir, int log_r, int log_s, int scale_log, int* rc);
+const u32x4* pass_table(frntt_ctx* ctx, int dir, int log_r, int log_s, int scale_log, int coset, int* rc);
 // Does the first pass of `plan` read a twiddle table (so that an inverse
 // transform can take N^-1 from it)?
 bool first_pass_scaled(const Plan& plan);

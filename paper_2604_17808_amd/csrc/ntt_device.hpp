@@ -57,7 +57,9 @@ struct PassParams {
   int lev_log[kMaxLevels];
   int engine;       // 0: butterfly stages, 1: MFMA levels (lev_log)
   int dir;          // 0: forward roots, 1: inverse roots
-  int coset_pre;    // first pass of a coset transform: x_n *= g^n on load
+  int coset_pre;    // first pass of a coset transform: x_n *= g^n on load; 1: g^n from the
+                   // split tables; 2: g^(j 2^log_s) for line element j from the tail of the
+                   // pass table, whose entries carry the line's g^rest
   int post;         // last pass: 0 none, 1 scale by N^-1, 2 scale by N^-1 g^-k, 3 scale by g^-k
                    // (2^-log_n then rides in the first pass's twiddle table)
   int xcd_remap;    // map consecutive logical workgroups onto one XCD

@@ -61,7 +61,8 @@ __device__ FRNTT_INLINE void load_lines(u32x4* lds, const PassParams& P, const D
       const LineMap mp = map_line(P, wg * G + line);
       const int64_t idx = mp.in_base + ((int64_t)n << mp.in_shift);
       fr_t x = ld_elem(P.src, idx);
-      if (P.coset_pre) x = mont_mul(x, coset_pow(T, 0, (uint32_t)(idx & nmask)));
+      if (P.coset_pre == 1) x = mont_mul(x, coset_pow(T, 0, (uint32_t)(idx & nmask)));
+      else if (P.coset_pre == 2) x = mont_mul(x, ld_elem(P.pass_tw, (1ll << (P.log_r + P.log_s)) + n));
       lds_st(lds, e, x);
     }
   } else {

@@ -74,13 +74,26 @@ __global__ void zero_words_kernel(unsigned int* p, int64_t n) {
 // of an inverse transform is one constant factor on every output, so the
 // first pass can apply it with its twiddle instead of the last pass spending
 // a product on it.
-__global__ void pass_twiddle_kernel(u32x4* dst, DevTables T, int dir, int log_r, int log_s, int scale_log) {
+// With coset = 1 (first pass of a coset transform, element index
+// n = rest + j 2^log_s): g^n = g^rest * (g^(2^log_s))^j, and g^rest is
+// constant along the line, so it commutes with the line's DFT and rides in
+// the entry [k][rest]; 2^log_r more entries at N + j hold (g^(2^log_s))^j for
+// the load-time pre-scale, one product per element instead of two.
+__global__ void pass_twiddle_kernel(u32x4* dst, DevTables T, int dir, int log_r, int log_s, int scale_log,
+                                    int coset) {
   const int64_t n = 1ll << (log_r + log_s);
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t total = n + (coset ? (1ll << log_r) : 0);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (i >= n) {
+      st_elem(dst, i, coset_pow(T, 0, (uint32_t)((i - n) << log_s)));
+      continue;
+    }
     const uint64_t k = (uint64_t)i >> log_s;
     const uint64_t rest = (uint64_t)i & ((1ull << log_s) - 1);
     fr_t w = pow_tw(T, dir, log_r + log_s, rest * k);
     if (scale_log >= 0) w = mont_mul(ld_elem(T.ninv, scale_log), w);
+    if (coset) w = mont_mul(coset_pow(T, 0, (uint32_t)rest), w);
     st_elem(dst, i, w);
   }
 }

@@ -43,7 +43,8 @@ def test_work_epilogues_and_large_passes():
     assert bench.algorithmic_work([12], kind=3)[0]["mads"] == 3 * 20 + 2 * 162 + 3 * 162
     assert bench.algorithmic_work([9, 9, 8], kind=1)[2]["mads"] == 2 * 20 + 162 + 162
     coset = bench.algorithmic_work([12, 12], kind=2)
-    assert coset[0]["mads"] == 3 * 20 + 3 * 162 + 2 * 162    # + coset pre-scale
+    assert coset[0]["mads"] == 3 * 20 + 3 * 162 + 162        # + coset pre-scale (table)
+    assert bench.algorithmic_work([12], kind=2)[0]["mads"] == 3 * 20 + 2 * 162 + 2 * 162
     # above the table limit the pass twiddle takes two products and no table read
     big = bench.algorithmic_work([10, 9, 9], kind=0)
     assert big[0]["mads"] == 3 * 20 + 2 * 162 + 2 * 162 and big[0]["hbm_bytes"] == 64

@@ -109,29 +109,31 @@ def test_plans_bit_identical(ctx, algo, plan):
         ctx.set_plan(algo, 16, [])
 
 
-def test_inverse_kinds_use_their_own_first_pass_table():
-    """N^-1 rides in the first pass's twiddle table of an inverse transform:
-    forward and inverse tables of one size are distinct, a coset kind shares
-    the table of the plain kind of its direction, and a single-pass
-    transform builds none."""
+def test_first_pass_tables_per_kind():
+    """The first pass's twiddle table differs per kind: an inverse kind's
+    entries carry N^-1, a forward coset kind's carry the line's g^rest and it
+    ends with 2^l pre-scale entries; a coset INTT shares the INTT's table,
+    and a single-pass transform builds none. Every kind stays exact."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     _say("pass tables per kind")
     c = fr.Context(0, max_log_n=20)
     try:
-        assert len(c.get_plan(fr.ALGO_AUTO, 16)) == 2   # one table, 2^16 entries
+        plan = c.get_plan(fr.ALGO_AUTO, 16)
+        assert len(plan) == 2                    # one table of 2^16 entries
+        t, tail = 32 << 16, 32 << plan[0]
         sizes = []
         for kind in (fr.FWD, fr.COSET, fr.INV, fr.COSET_INV):
             c.prepare(16, kind)
             sizes.append(c.table_bytes())
-        base = sizes[0] - (32 << 16)          # a 2^16 transform: one 2^16-entry table
-        assert sizes == [base + (32 << 16), base + (32 << 16), base + (64 << 16), base + (64 << 16)]
+        base = sizes[0] - t
+        assert sizes == [base + t, base + 2 * t + tail, base + 3 * t + tail, base + 3 * t + tail]
         c.prepare(12, fr.INV)
         assert c.table_bytes() == sizes[-1]
         x = inputs(12, 16, 1)
         for kind in range(4):
             assert np.array_equal(run(c, x, 16, kind), cref.transform(x, 16, kind))
-        assert c.table_bytes() == sizes[-1]   # the transforms used the prepared tables
+        assert c.table_bytes() == sizes[-1]      # the transforms used the prepared tables
     finally:
         torch.cuda.synchronize()
         c.close()
