@@ -102,7 +102,9 @@ def algorithmic_work(plan, kind=0):
         if p + 1 == len(plan) and kind == 1 and not folded:
             mads += MADS_PER_PRODUCT              # N^-1
         if p + 1 == len(plan) and kind == 3:
-            mads += (2 if folded else 3) * MADS_PER_PRODUCT   # g^-k (N^-1 g^-k)
+            # g^-K: one product from the first pass's table tail (two passes),
+            # two from the split tables, three with N^-1
+            mads += (1 if folded and len(plan) == 2 else 2 if folded else 3) * MADS_PER_PRODUCT
         rest = sum(plan[p + 1:])
         # HBM: read and write every element; a non-last pass also reads its
         # twiddle table (one 32-byte entry per element) when the library keeps one

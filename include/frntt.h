@@ -164,9 +164,9 @@ size_t frntt_scratch_bytes(int log_n, int batch);
  * inverse kind reads a table whose entries also carry N^-1 (its last pass then
  * skips that product); that of a forward coset kind carries the per-line part
  * g^rest of the coset factor and ends with 2^l entries of its per-element part
- * for the pre-scale. So FWD, COSET and INV of one size use three distinct
- * tables, and COSET_INV shares the INV table. Synchronous. Errors: EINVAL,
- * ERANGE, ENOMEM, EHIP. */
+ * for the pre-scale; that of a two-pass COSET_INV carries N^-1 g^-k and ends
+ * with the factors of the last pass's epilogue. So each kind of one size has
+ * its own table. Synchronous. Errors: EINVAL, ERANGE, ENOMEM, EHIP. */
 int frntt_prepare(frntt_ctx *ctx, int log_n, int kind);
 
 /* Device bytes held by the context's tables, including the pass-twiddle

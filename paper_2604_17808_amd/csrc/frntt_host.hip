@@ -163,6 +163,10 @@ int build_passes(frntt_ctx* ctx, const Plan& plan_in, int log_n, int batch, int 
   // a coset transform whose first pass reads a twiddle table takes the
   // per-line part of g^n from that table and the rest from its tail
   const bool coset_fold = kind == FRNTT_COSET && first_pass_scaled(plan);
+  // a two-pass coset INTT also takes g^-k of the first pass's output digit
+  // from that table and the rest of g^-K from its tail
+  const bool coset_inv_fold = kind == FRNTT_COSET_INV && plan.n_pass == 2 && first_pass_scaled(plan);
+  const u32x4* first_tw = nullptr;
   int d = 0;
   for (int p = 0; p < plan.n_pass; ++p) {
     const int l = plan.pass_log[p];
@@ -191,14 +195,17 @@ int build_passes(frntt_ctx* ctx, const Plan& plan_in, int log_n, int batch, int 
     P.coset_pre = (first && kind == FRNTT_COSET) ? (coset_fold ? 2 : 1) : 0;
     P.post = 0;
     if (last && kind == FRNTT_INV) P.post = fold ? 0 : 1;
-    if (last && kind == FRNTT_COSET_INV) P.post = fold ? 3 : 2;
+    if (last && kind == FRNTT_COSET_INV) P.post = coset_inv_fold ? 4 : fold ? 3 : 2;
+    P.post_tw = P.post == 4 ? first_tw + 2 * ((int64_t)1 << log_n) : nullptr;
     const int64_t lines = ((int64_t)batch << log_n) >> l;
     P.wg_count = lines >> lg;
     P.xcd_remap = 1;
     P.pass_tw = nullptr;
     if (!last) {
       int rc = FRNTT_OK;
-      P.pass_tw = pass_table(ctx, dir, l, s, first && fold ? log_n : -1, first && coset_fold ? 1 : 0, &rc);
+      const int coset = !first ? 0 : coset_fold ? 1 : coset_inv_fold ? 2 : 0;
+      P.pass_tw = pass_table(ctx, dir, l, s, first && fold ? log_n : -1, coset, &rc);
+      if (first) first_tw = P.pass_tw;
       if (rc != FRNTT_OK) return rc;
     }
     out->push_back(P);
@@ -219,7 +226,7 @@ static int pass_table_key(int dir, int log_r, int log_s, int scale_log, int cose
 }
 
 static size_t pass_table_entries(int log_r, int log_s, int coset) {
-  return ((size_t)1 << (log_r + log_s)) + (coset ? ((size_t)1 << log_r) : 0);
+  return ((size_t)1 << (log_r + log_s)) + (coset == 1 ? ((size_t)1 << log_r) : coset == 2 ? ((size_t)1 << log_s) : 0);
 }
 
 const u32x4* pass_table(frntt_ctx* ctx, int dir, int log_r, int log_s, int scale_log, int coset, int* rc) {
@@ -263,6 +270,7 @@ size_t pending_pass_table_bytes(frntt_ctx* ctx, const Plan& plan, int kind) {
   const int dir = (kind == FRNTT_INV || kind == FRNTT_COSET_INV) ? 1 : 0;
   const bool fold = dir == 1 && first_pass_scaled(plan);
   const bool coset_fold = kind == FRNTT_COSET && first_pass_scaled(plan);
+  const bool coset_inv_fold = kind == FRNTT_COSET_INV && plan.n_pass == 2 && first_pass_scaled(plan);
   size_t bytes = 0;
   std::lock_guard<std::mutex> lk(ctx->tw_mu);
   for (int p = 0; p + 1 < plan.n_pass; ++p) {
@@ -271,7 +279,7 @@ size_t pending_pass_table_bytes(frntt_ctx* ctx, const Plan& plan, int kind) {
     const int l = plan.pass_log[p];
     if (l + s > kPassTableMaxLog) continue;
     const int scale_log = p == 0 && fold ? l + s : -1;
-    const int coset = p == 0 && coset_fold ? 1 : 0;
+    const int coset = p != 0 ? 0 : coset_fold ? 1 : coset_inv_fold ? 2 : 0;
     if (!ctx->pass_tw.count(pass_table_key(dir, l, s, scale_log, coset)))
       bytes += 32 * pass_table_entries(l, s, coset);
   }

@@ -99,7 +99,9 @@ int build_passes(frntt_ctx* ctx, const Plan& plan, int log_n, int batch, int kin
                  void* data, void* scratch, std::vector<PassParams>* out, int algo);
 // Pass-twiddle table w_(2^(log_r + log_s))^(rest * k) at [k][rest] for a
 // non-last pass, times 2^-scale_log when scale_log >= 0, times g^rest with
-// 2^log_r pre-scale entries (g^(2^log_s))^j appended when coset != 0 (built
+// 2^log_r pre-scale entries (g^(2^log_s))^j appended when coset == 1, times
+// g^-k with 2^log_s epilogue entries (g^-(2^log_r))^k' appended when
+// coset == 2 (built
 // and cached per (dir, log_r, log_s, scale_log, coset) on first use), or
 // nullptr when it would
 // exceed kPassTableMaxLog entries (the pass then forms each twiddle from the

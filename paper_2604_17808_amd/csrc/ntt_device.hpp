@@ -61,9 +61,12 @@ struct PassParams {
                    // split tables; 2: g^(j 2^log_s) for line element j from the tail of the
                    // pass table, whose entries carry the line's g^rest
   int post;         // last pass: 0 none, 1 scale by N^-1, 2 scale by N^-1 g^-k, 3 scale by g^-k
-                   // (2^-log_n then rides in the first pass's twiddle table)
+                   // (2^-log_n then rides in the first pass's twiddle table), 4 scale by
+                   // post_tw[K >> log_d] = g^-(K - K mod 2^log_d) (N^-1 g^-(K mod 2^log_d)
+                   // ride in the first pass's table; two-pass plans)
   int xcd_remap;    // map consecutive logical workgroups onto one XCD
   const u32x4* pass_tw;  // non-last pass: table of its twiddles at [k][rest], or nullptr
+  const u32x4* post_tw;  // last pass with post 4: factor of output K at [K >> log_d]
 };
 
 // Descriptor tables of one persistent batch launch (see ntt_batch_kernel).

@@ -114,6 +114,8 @@ __device__ FRNTT_INLINE void store_lines(const u32x4* lds, const PassParams& P, 
     } else if (P.post == 3) {
       const uint32_t idx = (uint32_t)(mp.poly_off + ((int64_t)k << mp.out_shift));
       y = mont_mul(coset_pow(T, 1, idx), y);
+    } else if (P.post == 4) {
+      y = mont_mul(ld_elem(P.post_tw, k), y);
     }
     st_elem(P.dst, mp.out_base + ((int64_t)k << mp.out_shift), y);
   }
@@ -322,7 +324,7 @@ struct PairWork {
     if constexpr (S < P0) {
       mg.template step<S>();
       if constexpr (S == P0 - 1) y = mg.result();
-    } else if constexpr (KIND == 1 || KIND == 3 || KIND == 5) {
+    } else if constexpr (KIND == 1 || KIND == 3 || KIND == 5 || KIND == 7) {
       prod<S - P0>(tw, y, y);
     } else if constexpr (KIND == 2 || KIND == 6) {
       if constexpr (S < P1) prod<S - P0>(tw, tw2, tw);
@@ -416,6 +418,7 @@ struct TileLoop {
         }
         if (KIND == 5) wk.tw = ld_elem(P.pass_tw, ((int64_t)(kk + (k << g.pprev_log)) << P.log_s) + rest);
         if (KIND == 3) wk.tw = ld_elem(Tb.ninv, P.log_n);
+        if (KIND == 7) wk.tw = ld_elem(P.post_tw, kk + (k << g.pprev_log));
         if (KIND == 4 || KIND == 6) {
           const uint32_t idx = (uint32_t)(mp.poly_off + ((int64_t)(kk + (k << g.pprev_log)) << mp.out_shift));
           wk.tw = ld_elem(Tb.g_lo[1], idx & ((1u << kSplit) - 1));
@@ -490,6 +493,7 @@ __device__ FRNTT_INLINE void mfma_level_any(u32x4* lds, i32x4* blk, const PassPa
   else if (P.post == 1) mfma_level<M, TPW, 3>(lds, blk, P, T, g, false, wg);
   else if (P.post == 2) mfma_level<M, TPW, 4>(lds, blk, P, T, g, false, wg);
   else if (P.post == 3) mfma_level<M, TPW, 6>(lds, blk, P, T, g, false, wg);
+  else if (P.post == 4) mfma_level<M, TPW, 7>(lds, blk, P, T, g, false, wg);
   else mfma_level<M, TPW, 0>(lds, blk, P, T, g, false, wg);
 }
 
@@ -592,6 +596,7 @@ __device__ FRNTT_INLINE void plan_last_level(u32x4* lds, i32x4* blk, const PassP
   else if (P.post == 1) mfma_level<M, TPW, 3>(lds, blk, P, T, g, false, wg);
   else if (P.post == 2) mfma_level<M, TPW, 4>(lds, blk, P, T, g, false, wg);
   else if (P.post == 3) mfma_level<M, TPW, 6>(lds, blk, P, T, g, false, wg);
+  else if (P.post == 4) mfma_level<M, TPW, 7>(lds, blk, P, T, g, false, wg);
   else mfma_level<M, TPW, 0>(lds, blk, P, T, g, false, wg);
 }
 

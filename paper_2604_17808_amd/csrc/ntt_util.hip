@@ -79,21 +79,27 @@ __global__ void zero_words_kernel(unsigned int* p, int64_t n) {
 // constant along the line, so it commutes with the line's DFT and rides in
 // the entry [k][rest]; 2^log_r more entries at N + j hold (g^(2^log_s))^j for
 // the load-time pre-scale, one product per element instead of two.
+// With coset = 2 (first pass of a two-pass coset INTT, output index
+// K = k + 2^log_r k'): g^-K = g^-k * (g^-(2^log_r))^k', and g^-k rides in
+// the entries of row k; 2^log_s more entries at N + k' hold
+// (g^-(2^log_r))^k' for the last pass's epilogue (one product, not two).
 __global__ void pass_twiddle_kernel(u32x4* dst, DevTables T, int dir, int log_r, int log_s, int scale_log,
                                     int coset) {
   const int64_t n = 1ll << (log_r + log_s);
-  const int64_t total = n + (coset ? (1ll << log_r) : 0);
+  const int64_t total = n + (coset == 1 ? (1ll << log_r) : coset == 2 ? (1ll << log_s) : 0);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * blockDim.x) {
     if (i >= n) {
-      st_elem(dst, i, coset_pow(T, 0, (uint32_t)((i - n) << log_s)));
+      const uint32_t e = coset == 1 ? (uint32_t)((i - n) << log_s) : (uint32_t)((i - n) << log_r);
+      st_elem(dst, i, coset_pow(T, coset == 1 ? 0 : 1, e));
       continue;
     }
     const uint64_t k = (uint64_t)i >> log_s;
     const uint64_t rest = (uint64_t)i & ((1ull << log_s) - 1);
     fr_t w = pow_tw(T, dir, log_r + log_s, rest * k);
     if (scale_log >= 0) w = mont_mul(ld_elem(T.ninv, scale_log), w);
-    if (coset) w = mont_mul(coset_pow(T, 0, (uint32_t)rest), w);
+    if (coset == 1) w = mont_mul(coset_pow(T, 0, (uint32_t)rest), w);
+    if (coset == 2) w = mont_mul(coset_pow(T, 1, (uint32_t)k), w);
     st_elem(dst, i, w);
   }
 }

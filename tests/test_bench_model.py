@@ -37,7 +37,8 @@ def test_work_epilogues_and_large_passes():
     inv = bench.algorithmic_work([12, 12], kind=1)
     assert inv[1]["mads"] == 3 * 20 + 2 * 162
     cinv = bench.algorithmic_work([12, 12], kind=3)
-    assert cinv[1]["mads"] == 3 * 20 + 2 * 162 + 2 * 162     # g^-k
+    assert cinv[1]["mads"] == 3 * 20 + 2 * 162 + 162         # g^-K from the table's tail
+    assert bench.algorithmic_work([6, 5, 5], kind=3)[2]["mads"] == 2 * 20 + 162 + 2 * 162
     # a single pass (no table) and a plan above the table limit keep it
     assert bench.algorithmic_work([12], kind=1)[0]["mads"] == 3 * 20 + 2 * 162 + 162
     assert bench.algorithmic_work([12], kind=3)[0]["mads"] == 3 * 20 + 2 * 162 + 3 * 162

@@ -111,9 +111,10 @@ def test_plans_bit_identical(ctx, algo, plan):
 
 def test_first_pass_tables_per_kind():
     """The first pass's twiddle table differs per kind: an inverse kind's
-    entries carry N^-1, a forward coset kind's carry the line's g^rest and it
-    ends with 2^l pre-scale entries; a coset INTT shares the INTT's table,
-    and a single-pass transform builds none. Every kind stays exact."""
+    entries carry N^-1; a forward coset kind's carry the line's g^rest and it
+    ends with 2^l0 pre-scale entries; a two-pass coset INTT's carry N^-1 g^-k
+    and it ends with 2^l1 epilogue entries. A single-pass transform builds
+    none. Every kind stays exact."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     _say("pass tables per kind")
@@ -121,13 +122,13 @@ def test_first_pass_tables_per_kind():
     try:
         plan = c.get_plan(fr.ALGO_AUTO, 16)
         assert len(plan) == 2                    # one table of 2^16 entries
-        t, tail = 32 << 16, 32 << plan[0]
+        t, tail, tail_inv = 32 << 16, 32 << plan[0], 32 << plan[1]
         sizes = []
         for kind in (fr.FWD, fr.COSET, fr.INV, fr.COSET_INV):
             c.prepare(16, kind)
             sizes.append(c.table_bytes())
         base = sizes[0] - t
-        assert sizes == [base + t, base + 2 * t + tail, base + 3 * t + tail, base + 3 * t + tail]
+        assert sizes == [base + t, base + 2 * t + tail, base + 3 * t + tail, base + 4 * t + tail + tail_inv]
         c.prepare(12, fr.INV)
         assert c.table_bytes() == sizes[-1]
         x = inputs(12, 16, 1)
