@@ -34,13 +34,18 @@ def _rand_vec(n, seed):
 
 # ---------------------------------------------------------------- field facts
 
-def test_modulus_matches_golden_and_is_prime():
+def _golden_field():
     vals = {}
     with open(os.path.join(GOLDEN, "bn254_fr.txt")) as f:
         for line in f:
             if line.strip() and not line.startswith("#"):
                 k, v = line.split()
-                vals[k] = int(v)
+                vals[k] = int(v, 0)
+    return vals
+
+
+def test_modulus_matches_golden_and_is_prime():
+    vals = _golden_field()
     assert F.R_MOD == vals["modulus_dec"]
     assert si.modulus() == vals["modulus_dec"]
     assert sympy.isprime(R)
@@ -60,6 +65,59 @@ def test_root_properties(log_n):
     assert pow(w, n, R) == 1
     assert pow(w, n // 2, R) == R - 1          # w^(N/2) = -1
     assert (w * F.root_of_unity(n, inverse=True)) % R == 1
+
+
+@pytest.mark.parametrize("log_n", [10, 20, 24, 28])
+def test_python_roots_match_golden_hex(log_n):
+    """The Python oracle's w_N equals the hex value written out independently."""
+    vals = _golden_field()
+    assert F.root_of_unity(1 << log_n) == vals[f"omega_2e{log_n}"]
+
+
+def test_python_inverses_and_radix_match_golden_hex():
+    vals = _golden_field()
+    assert F.inv_mod(1 << 10) == vals["inv_2e10"]
+    assert F.inv_mod(F.COSET_SHIFT) == vals["inv_5"]
+    assert pow(2, 256, R) == vals["two256_mod_r"]
+    # and the defining properties, so that a wrong hex value cannot pass
+    assert (vals["inv_2e10"] << 10) % R == 1 and (vals["inv_5"] * 5) % R == 1
+
+
+@pytest.mark.parametrize("log_n", [10, 20, 24])
+def test_c_oracle_roots_and_scale_match_golden(log_n):
+    """The C oracle reaches the same constants through its own arithmetic:
+    output 1 of the transform of delta_1 is w_N (sum_n delta_1[n] w^(kn) at
+    k = 1), output 0 of the inverse transform of delta_0 is N^-1, and output 1
+    of the coset transform of delta_1 is g w_N."""
+    vals = _golden_field()
+    n = 1 << log_n
+    d1 = np.zeros((n, 4), dtype=np.uint64)
+    d1[1, 0] = 1
+    w = si.to_ints(cref.eval_output(d1, log_n, 1, 0))[0]
+    assert w == vals[f"omega_2e{log_n}"]
+    assert si.to_ints(cref.eval_output(d1, log_n, 1, 2))[0] == (5 * w) % R
+    d0 = np.zeros((n, 4), dtype=np.uint64)
+    d0[0, 0] = 1
+    ninv = si.to_ints(cref.eval_output(d0, log_n, 0, 1))[0]
+    assert (ninv * n) % R == 1
+    if log_n == 10:
+        assert ninv == vals["inv_2e10"]
+    # the full transform of delta_1 at N = 2^10 is the power table of w_N
+    if log_n == 10:
+        got = si.to_ints(cref.transform(d1, log_n, 0))
+        assert got == [pow(vals["omega_2e10"], k, R) for k in range(n)]
+
+
+def test_c_oracle_large_sizes_against_python_definition():
+    """Sampled outputs of the C radix-2 transform at 2^16 and 2^20, every
+    kind, against the Python big-integer definition (Horner, O(N) each)."""
+    for log_n, ks in ((16, (0, 1, 40000, (1 << 16) - 1)), (20, (0, 777777))):
+        x = si.polynomial(1000 + log_n, log_n)
+        xi = si.to_ints(x)
+        for kind in range(4):
+            full = cref.transform(x, log_n, kind)
+            for k in ks:
+                assert si.to_ints(full[k:k + 1])[0] == F.eval_output(xi, k, kind), (log_n, kind, k)
 
 
 @pytest.mark.parametrize("log_n", [1, 4, 8, 12])
@@ -263,7 +321,7 @@ def test_pins_catch_planted_mistakes(kind):
 
 # ------------------------------------------------------ C oracle vs Python
 
-@pytest.mark.parametrize("log_n", [0, 1, 2, 5, 9, 12])
+@pytest.mark.parametrize("log_n", [0, 1, 2, 5, 9, 12, 13, 14])
 @pytest.mark.parametrize("kind", [0, 1, 2, 3])
 def test_c_oracle_matches_python(log_n, kind):
     batch = 3 if log_n <= 9 else 1
