@@ -23,9 +23,16 @@
  * and its scratch space.
  *
  * Asynchrony: every transform call is enqueued on `stream` (a hipStream_t;
- * NULL means the null stream) and returns at once. Argument errors are
- * returned synchronously before anything is enqueued. A failed HIP launch
- * returns FRNTT_EHIP and frntt_last_hip_error() gives the hipError_t.
+ * NULL means the null stream) and returns at once, with two exceptions that
+ * happen at most once per context: the first transform of a (size, kind,
+ * plan) builds that plan's pass-twiddle table (allocation plus a synchronous
+ * device fill; frntt_prepare does it ahead of time), and the first transform
+ * on a stream that needs more scratch than the stream has allocates it.
+ * Inside a hipGraph stream capture neither may happen: such a call returns
+ * FRNTT_ESTATE and enqueues nothing (call frntt_prepare and one transform of
+ * that size on the stream before capturing). Argument errors are returned
+ * synchronously before anything is enqueued. A failed HIP launch returns
+ * FRNTT_EHIP and frntt_last_hip_error() gives the hipError_t.
  *
  * Preconditions: inputs must be canonical (< r). With the FRNTT_VALIDATE
  * context flag a device check runs before each transform; a violation is
@@ -75,7 +82,11 @@ enum { FRNTT_ALGO_AUTO = 0, FRNTT_ALGO_BUTTERFLY = 1, FRNTT_ALGO_FOURSTEP_MFMA =
 
 /* Context flags. */
 enum {
-    FRNTT_VALIDATE = 1u << 0  /* check inputs < r on the device before transforming */
+    FRNTT_VALIDATE = 1u << 0,       /* check inputs < r on the device before transforming */
+    FRNTT_SPLIT_TWIDDLES = 1u << 1  /* keep no N-entry pass-twiddle tables: every pass twiddle
+                                     * (and coset factor) is formed from the two 2^14-entry
+                                     * split tables with one more product. For contexts that
+                                     * must keep their table memory small (a few MiB); slower. */
 };
 
 /* Create a context on HIP device `hip_device` for sizes up to 2^max_log_n
@@ -115,6 +126,14 @@ int frntt_set_plan(frntt_ctx *ctx, int algo, int log_n, const int *pass_logs, in
  * or an error. */
 int frntt_get_plan(const frntt_ctx *ctx, int algo, int log_n, int *pass_logs, int cap);
 
+/* The level split the matrix form uses inside HBM pass `pass` of a single
+ * transform of 2^log_n elements with the plan in use (default, override or
+ * tuned): writes up to `cap` log2 radices and returns how many levels there
+ * are, or 0 if that pass runs on the butterfly engine (the algorithm is the
+ * butterfly form, or the pass's tile is below 4096 elements). Errors: EINVAL,
+ * ERANGE. */
+int frntt_get_plan_levels(const frntt_ctx *ctx, int algo, int log_n, int pass, int *levels, int cap);
+
 /* One job of an uneven batch: a polynomial of 2^log_n elements at `data`. */
 typedef struct {
     void *data;
@@ -126,7 +145,9 @@ typedef struct {
  * place with ONE persistent kernel launch. The descriptors are copied before
  * the call returns; the data buffers must stay alive until the stream passes
  * the call. Jobs must not overlap in memory. Errors as for ntt_transform,
- * per job, plus EINVAL for n_jobs < 0 or jobs == NULL with n_jobs > 0. */
+ * per job, plus EINVAL for n_jobs < 0 or jobs == NULL with n_jobs > 0, and
+ * ESTATE inside a stream capture (the descriptor upload waits on the host;
+ * ntt_batch_graph is the capturable form). */
 int ntt_batch(frntt_ctx *ctx, const frntt_job *jobs, int n_jobs, void *stream);
 
 /* Graph form of ntt_batch for repeated identical batches: the first call for
@@ -134,9 +155,16 @@ int ntt_batch(frntt_ctx *ctx, const frntt_job *jobs, int n_jobs, void *stream);
  * same list replay it. Results are identical to ntt_batch. */
 int ntt_batch_graph(frntt_ctx *ctx, const frntt_job *jobs, int n_jobs, void *stream);
 
-/* Autotuner: time the candidate plans (algorithm, pass split, launch shape)
- * for one size and batch on `stream`, keep the fastest in the context, and
- * return it through the out-parameters (any may be NULL). */
+/* Autotuner: time forward transforms of one size and batch on `stream` for
+ * every candidate plan: algorithm x split into HBM passes (one pass up to
+ * 2^12, two passes of at least 2^4 each, three balanced passes from 2^15) x,
+ * for the matrix form, the order of the level radices inside its 2^10 and
+ * 2^11 passes ([4,3,3], [3,4,3], [3,3,4]; [4,4,3], [3,4,4], [4,3,4]). The
+ * median of five runs decides. Keeps the fastest in the context (used by
+ * transforms and batches of that size, every kind) and returns it through the
+ * out-parameters (any may be NULL). Pass-twiddle tables that only losing
+ * candidates built are freed again (after waiting for the device): do not
+ * tune a size while other threads transform that size. Synchronous. */
 int frntt_tune(frntt_ctx *ctx, int log_n, int batch, int *best_algo, int *best_passes,
                float *best_ms, void *stream);
 /* Save / load the tuned choices as a small JSON file. */
@@ -212,6 +240,10 @@ int frntt_server_set_release_on_done(frntt_server *srv, int on);
 /* Counters: requests completed, batches launched, peak bytes in flight. */
 int frntt_server_stats(frntt_server *srv, uint64_t *completed, uint64_t *batches,
                        uint64_t *peak_bytes);
+/* Largest number of batches (each one persistent launch on its own slot
+ * stream) and of requests that were launched and not yet complete at the
+ * same time: batches > 1 means launches were in flight together. */
+int frntt_server_peak_inflight(frntt_server *srv, uint64_t *batches, uint64_t *requests);
 /* Cancel requests not yet admitted, wait for running batches, stop the
  * worker and free everything. */
 int frntt_server_destroy(frntt_server *srv);

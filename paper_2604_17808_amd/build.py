@@ -49,6 +49,25 @@ def _compile(src: str, force: bool) -> str:
     return obj
 
 
+PEAKS_SRC = os.path.join(HERE, "peaks", "peaks.hip")
+PEAKS_LIB = os.path.join(HERE, "libfrntt_peaks.so")
+
+
+def build_peaks(force: bool = True) -> str:
+    """The rate microbenchmark the benchmark's roofline uses (not part of the
+    transform library)."""
+    if not force and os.path.exists(PEAKS_LIB) and os.path.getmtime(PEAKS_LIB) >= os.path.getmtime(PEAKS_SRC):
+        return PEAKS_LIB
+    tmp = PEAKS_LIB + ".tmp"
+    cmd = [HIPCC, *COMMON, "-shared", PEAKS_SRC, "-o", tmp]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed for peaks.hip")
+    os.replace(tmp, PEAKS_LIB)
+    return PEAKS_LIB
+
+
 def build(force: bool = True, jobs: int = 8) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = _sources()
@@ -58,6 +77,7 @@ def build(force: bool = True, jobs: int = 8) -> str:
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp, "-lpthread"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    build_peaks(force)
     return LIB
 
 

@@ -143,7 +143,11 @@ struct MontMul {
     t[8] = 0;
     t[0] += c;
   }
-  __device__ FRNTT_INLINE fr_t finish() const {
+  __device__ FRNTT_INLINE fr_t finish() const { return fr_reduce_once(finish_lazy()); }
+  // The product before the final subtraction: a value below 2r (< 2^255),
+  // congruent to a * b * 2^-261. Enough where the next consumer only needs
+  // 32 bytes of a value below 2^256 (the byte digits of the matrix form).
+  __device__ FRNTT_INLINE fr_t finish_lazy() const {
     // carry-propagate the columns into 29-bit limbs, then pack 32-bit words
     uint32_t l[9];
     uint64_t c = 0;
@@ -166,7 +170,7 @@ struct MontMul {
       if (have + 29 < 32 && k + 2 < 9) v |= l[k + 2] << (have + 29);
       o.w[i] = v;
     }
-    return fr_reduce_once(o);
+    return o;
   }
 };
 

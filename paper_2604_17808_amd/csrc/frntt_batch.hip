@@ -58,11 +58,15 @@ DevLayout layout_for(size_t np, size_t ni) {
   return L;
 }
 
-// Validate the jobs and compute their scratch needs (bytes, per job offset).
+// Validate the jobs, fix the algorithm and plan of each (read once, so that a
+// concurrent plan change cannot make the scratch layout and the passes
+// disagree) unless `given` supplies them, and compute the scratch needs
+// (bytes, per job offset).
 int check_jobs(frntt_ctx* ctx, const frntt_job* jobs, int n_jobs, std::vector<size_t>* scratch_off,
-               size_t* scratch_total) {
+               size_t* scratch_total, std::vector<JobPlan>* plans, const JobPlan* given = nullptr) {
   if (!ctx || n_jobs < 0 || (n_jobs > 0 && !jobs)) return FRNTT_EINVAL;
   scratch_off->assign((size_t)n_jobs, 0);
+  plans->assign((size_t)n_jobs, JobPlan{});
   size_t tot = 0;
   for (int j = 0; j < n_jobs; ++j) {
     const frntt_job& jb = jobs[j];
@@ -71,27 +75,29 @@ int check_jobs(frntt_ctx* ctx, const frntt_job* jobs, int n_jobs, std::vector<si
     if (jb.log_n < 0 || jb.log_n > ctx->max_log_n) return FRNTT_ERANGE;
     if (((uintptr_t)jb.data & 31) != 0) return FRNTT_EALIGN;
     if (jb.log_n == 0) continue;
-    const int algo = effective_algo(ctx, jb.log_n, FRNTT_ALGO_AUTO);
-    const Plan plan = plan_for(ctx, algo, jb.log_n);
+    JobPlan& jp = (*plans)[(size_t)j];
+    if (given) jp = given[j];
+    else resolve_plan(ctx, FRNTT_ALGO_AUTO, jb.log_n, &jp.algo, &jp.plan);
+    if (check_plan_valid(jp.plan, jb.log_n) != FRNTT_OK) return FRNTT_EINVAL;
     (*scratch_off)[j] = tot;
-    tot += scratch_bytes_for(jb.log_n, 1, plan.n_pass);
+    tot += scratch_bytes_for(jb.log_n, 1, jp.plan.n_pass);
   }
   *scratch_total = tot;
   return FRNTT_OK;
 }
 
 int build_batch(frntt_ctx* ctx, const frntt_job* jobs, int n_jobs, const std::vector<void*>& scratch,
-                BatchBuild* B) {
+                const std::vector<JobPlan>& plans, BatchBuild* B, bool capturing) {
   std::vector<std::vector<int>> job_passes((size_t)n_jobs);
   int max_pass = 0;
   for (int j = 0; j < n_jobs; ++j) {
     const frntt_job& jb = jobs[j];
     if (jb.log_n == 0) continue;
-    const int algo = effective_algo(ctx, jb.log_n, FRNTT_ALGO_AUTO);
-    const Plan plan = plan_for(ctx, algo, jb.log_n);
+    const int algo = plans[(size_t)j].algo;
+    const Plan& plan = plans[(size_t)j].plan;
     std::vector<PassParams> pp;
     if (plan.n_pass > 1 && !scratch[(size_t)j]) return FRNTT_EINVAL;
-    int rc = build_passes(ctx, plan, jb.log_n, 1, jb.kind, jb.data, scratch[(size_t)j], &pp, algo);
+    int rc = build_passes(ctx, plan, jb.log_n, 1, jb.kind, jb.data, scratch[(size_t)j], &pp, algo, capturing);
     if (rc) return rc;
     int prev = -1;
     for (PassParams& P : pp) {
@@ -173,39 +179,48 @@ bool same_jobs(const std::vector<frntt_job>& a, const frntt_job* b, int n) {
 }  // namespace
 
 static int batch_launch_common(frntt_ctx* ctx, const frntt_job* jobs, int n_jobs,
-                               const std::vector<void*>& scratch, hipStream_t stream);
+                               const std::vector<void*>& scratch, const std::vector<JobPlan>& plans,
+                               hipStream_t stream);
 
 int batch_impl(frntt_ctx* ctx, const frntt_job* jobs, int n_jobs, hipStream_t stream) {
   std::vector<size_t> soff;
+  std::vector<JobPlan> plans;
   size_t stot = 0;
-  int rc = check_jobs(ctx, jobs, n_jobs, &soff, &stot);
+  int rc = check_jobs(ctx, jobs, n_jobs, &soff, &stot, &plans);
   if (rc) return rc;
   if (n_jobs == 0) return FRNTT_OK;
+  // the descriptor upload allocates and waits on the host: not capturable
+  // (ntt_batch_graph is the graph form)
+  if (stream_capturing(stream)) return FRNTT_ESTATE;
   void* base = nullptr;
   rc = get_scratch(ctx, stream, stot, &base);
   if (rc) return rc;
   std::vector<void*> scratch((size_t)n_jobs, nullptr);
   for (int j = 0; j < n_jobs; ++j) scratch[(size_t)j] = base ? (uint8_t*)base + soff[(size_t)j] : nullptr;
-  return batch_launch_common(ctx, jobs, n_jobs, scratch, stream);
+  return batch_launch_common(ctx, jobs, n_jobs, scratch, plans, stream);
 }
 
-// As batch_impl with caller-provided scratch per job (NULL for single-pass
-// sizes); used by the server, whose request buffers carry their scratch.
-int batch_impl_ws(frntt_ctx* ctx, const frntt_job* jobs, void* const* scratch_in, int n_jobs, hipStream_t stream) {
+// As batch_impl with caller-provided scratch and plan per job (scratch NULL
+// for single-pass plans); used by the server, whose request buffers carry
+// their scratch, sized for the plan fixed when the request was submitted.
+int batch_impl_ws(frntt_ctx* ctx, const frntt_job* jobs, void* const* scratch_in, const JobPlan* given, int n_jobs,
+                  hipStream_t stream) {
   std::vector<size_t> soff;
+  std::vector<JobPlan> plans;
   size_t stot = 0;
-  int rc = check_jobs(ctx, jobs, n_jobs, &soff, &stot);
+  int rc = check_jobs(ctx, jobs, n_jobs, &soff, &stot, &plans, given);
   if (rc) return rc;
   if (n_jobs == 0) return FRNTT_OK;
   std::vector<void*> scratch(scratch_in, scratch_in + n_jobs);
-  return batch_launch_common(ctx, jobs, n_jobs, scratch, stream);
+  return batch_launch_common(ctx, jobs, n_jobs, scratch, plans, stream);
 }
 
 static int batch_launch_common(frntt_ctx* ctx, const frntt_job* jobs, int n_jobs,
-                               const std::vector<void*>& scratch, hipStream_t stream) {
+                               const std::vector<void*>& scratch, const std::vector<JobPlan>& plans,
+                               hipStream_t stream) {
   int rc;
   BatchBuild B;
-  rc = build_batch(ctx, jobs, n_jobs, scratch, &B);
+  rc = build_batch(ctx, jobs, n_jobs, scratch, plans, &B, false);
   if (rc) return rc;
   if (B.item_pass.empty()) return FRNTT_OK;
   const DevLayout L = layout_for(B.passes.size(), B.item_pass.size());
@@ -249,8 +264,9 @@ static int batch_launch_common(frntt_ctx* ctx, const frntt_job* jobs, int n_jobs
 
 int batch_graph_impl(frntt_ctx* ctx, const frntt_job* jobs, int n_jobs, hipStream_t stream) {
   std::vector<size_t> soff;
+  std::vector<JobPlan> plans;
   size_t stot = 0;
-  int rc = check_jobs(ctx, jobs, n_jobs, &soff, &stot);
+  int rc = check_jobs(ctx, jobs, n_jobs, &soff, &stot, &plans);
   if (rc) return rc;
   if (n_jobs == 0) return FRNTT_OK;
   {
@@ -261,6 +277,8 @@ int batch_graph_impl(frntt_ctx* ctx, const frntt_job* jobs, int n_jobs, hipStrea
         return set_hip_error(ctx, e);
       }
   }
+  // a new job list allocates and captures: not possible inside a capture
+  if (stream_capturing(stream)) return FRNTT_ESTATE;
   // new entry: dedicated scratch and descriptors, captured once
   GraphEntry g;
   g.jobs.assign(jobs, jobs + n_jobs);
@@ -272,7 +290,7 @@ int batch_graph_impl(frntt_ctx* ctx, const frntt_job* jobs, int n_jobs, hipStrea
   BatchBuild B;
   std::vector<void*> scratch((size_t)n_jobs, nullptr);
   for (int j = 0; j < n_jobs; ++j) scratch[(size_t)j] = g.scratch ? (uint8_t*)g.scratch + soff[(size_t)j] : nullptr;
-  rc = build_batch(ctx, jobs, n_jobs, scratch, &B);
+  rc = build_batch(ctx, jobs, n_jobs, scratch, plans, &B, false);
   if (rc) {
     if (g.scratch) hipFree(g.scratch);
     return rc;
@@ -330,6 +348,14 @@ void candidate_splits(int log_n, std::vector<std::vector<int>>* out) {
       }
 }
 
+// The level orders the tuner tries for a pass radix 2^l (each has a plan
+// kernel; the first is the default split), or none.
+const std::vector<std::vector<int>>& level_orders(int l) {
+  static const std::vector<std::vector<int>> none, o10{{4, 3, 3}, {3, 4, 3}, {3, 3, 4}},
+      o11{{4, 4, 3}, {3, 4, 4}, {4, 3, 4}};
+  return l == 10 ? o10 : l == 11 ? o11 : none;
+}
+
 }  // namespace
 
 int tune_impl(frntt_ctx* ctx, int log_n, int batch, int* best_algo, int* best_passes, float* best_ms,
@@ -348,44 +374,70 @@ int tune_impl(frntt_ctx* ctx, int log_n, int batch, int* best_algo, int* best_pa
   TuneEntry best;
   best.ms = 1e30f;
   bool found = false;
-  // the tuner owns the overrides while it runs
-  Plan saved[3];
-  bool saved_has[3];
-  for (int a = 1; a <= 2; ++a) {
-    saved[a] = ctx->plan_override[a][log_n];
-    saved_has[a] = ctx->has_override[a][log_n];
-  }
+  const std::vector<int> tables_before = pass_table_keys(ctx);
+  // candidates run with explicit plans: the context's overrides and tuned
+  // plans are not touched until the winner is stored under ctx->mu
   for (int algo = FRNTT_ALGO_BUTTERFLY; rc == FRNTT_OK && algo <= FRNTT_ALGO_FOURSTEP_MFMA; ++algo) {
     for (const auto& sp : splits) {
-      rc = frntt_set_plan(ctx, algo, log_n, sp.data(), (int)sp.size());
-      if (rc) break;
-      // warm-up, then the median of 3
-      rc = transform_impl(ctx, buf, log_n, batch, FRNTT_FWD, algo, stream, nullptr, 0);
-      if (rc) break;
-      float t[3];
-      for (int r = 0; r < 3 && rc == FRNTT_OK; ++r) {
-        hipEventRecord(e0, stream);
-        rc = transform_impl(ctx, buf, log_n, batch, FRNTT_FWD, algo, stream, nullptr, 0);
-        hipEventRecord(e1, stream);
-        hipEventSynchronize(e1);
-        hipEventElapsedTime(&t[r], e0, e1);
+      // the matrix form also tries every level order of its 2^10 and 2^11 passes
+      std::vector<Plan> cands;
+      Plan base;
+      base.n_pass = (int)sp.size();
+      for (int i = 0; i < base.n_pass; ++i) base.pass_log[i] = sp[(size_t)i];
+      cands.push_back(base);
+      if (algo == FRNTT_ALGO_FOURSTEP_MFMA)
+        for (int p = 0; p < base.n_pass; ++p) {
+          const std::vector<std::vector<int>>& orders = level_orders(base.pass_log[p]);
+          if (orders.empty()) continue;
+          std::vector<Plan> grown;
+          for (const Plan& c : cands)
+            for (const auto& o : orders) {
+              Plan g = c;
+              g.lev_set[p] = true;
+              g.nlev[p] = (int)o.size();
+              for (int i = 0; i < (int)o.size(); ++i) g.lev_log[p][i] = o[(size_t)i];
+              grown.push_back(g);
+            }
+          cands.swap(grown);
+        }
+      for (const Plan& cand : cands) {
+        // warm-up, then the median of 5
+        rc = transform_plan(ctx, buf, log_n, batch, FRNTT_FWD, algo, cand, stream, nullptr, 0);
+        if (rc) break;
+        float t[5];
+        for (int r = 0; r < 5 && rc == FRNTT_OK; ++r) {
+          hipEventRecord(e0, stream);
+          rc = transform_plan(ctx, buf, log_n, batch, FRNTT_FWD, algo, cand, stream, nullptr, 0);
+          hipEventRecord(e1, stream);
+          hipEventSynchronize(e1);
+          hipEventElapsedTime(&t[r], e0, e1);
+        }
+        if (rc) break;
+        std::sort(t, t + 5);
+        if (t[2] < best.ms) {
+          best = TuneEntry{};
+          best.ms = t[2];
+          best.algo = algo;
+          best.n_pass = cand.n_pass;
+          for (int i = 0; i < 4; ++i) {
+            best.pass_log[i] = i < cand.n_pass ? cand.pass_log[i] : 0;
+            best.nlev[i] = cand.lev_set[i] ? cand.nlev[i] : 0;
+            for (int j = 0; j < 3; ++j) best.lev_log[i][j] = cand.lev_set[i] ? cand.lev_log[i][j] : 0;
+          }
+          found = true;
+        }
       }
       if (rc) break;
-      std::sort(t, t + 3);
-      if (t[1] < best.ms) {
-        best.ms = t[1];
-        best.algo = algo;
-        best.n_pass = (int)sp.size();
-        for (int i = 0; i < 4; ++i) best.pass_log[i] = i < (int)sp.size() ? sp[(size_t)i] : 0;
-        found = true;
-      }
     }
   }
-  for (int a = 1; a <= 2; ++a) {
-    ctx->plan_override[a][log_n] = saved[a];
-    ctx->has_override[a][log_n] = saved_has[a];
-  }
   hipStreamSynchronize(stream);
+  if (found) {
+    // release the pass-twiddle tables that only the losing candidates built
+    Plan chosen;
+    chosen.n_pass = best.n_pass;
+    for (int i = 0; i < 4; ++i) chosen.pass_log[i] = best.pass_log[i];
+    release_tuning_tables(ctx, tables_before, chosen);
+  }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   hipFree(buf);
@@ -406,6 +458,7 @@ int tune_save_impl(const frntt_ctx* ctx, const char* path) {
   if (!ctx || !path) return FRNTT_EINVAL;
   FILE* f = std::fopen(path, "w");
   if (!f) return FRNTT_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
   std::fprintf(f, "{\"format\": \"frntt-tune-1\", \"entries\": [");
   bool first = true;
   for (int l = 0; l <= 28; ++l) {
@@ -413,7 +466,13 @@ int tune_save_impl(const frntt_ctx* ctx, const char* path) {
     const TuneEntry& t = ctx->tuned[l];
     std::fprintf(f, "%s\n  {\"log_n\": %d, \"algo\": %d, \"passes\": [", first ? "" : ",", l, t.algo);
     for (int i = 0; i < t.n_pass; ++i) std::fprintf(f, "%s%d", i ? ", " : "", t.pass_log[i]);
-    std::fprintf(f, "], \"ms\": %.6f}", t.ms);
+    std::fprintf(f, "], \"ms\": %.6f, \"levels\": [", t.ms);
+    for (int i = 0; i < t.n_pass; ++i) {
+      std::fprintf(f, "%s[", i ? ", " : "");
+      for (int j = 0; j < t.nlev[i]; ++j) std::fprintf(f, "%s%d", j ? ", " : "", t.lev_log[i][j]);
+      std::fprintf(f, "]");
+    }
+    std::fprintf(f, "]}");
     first = false;
   }
   std::fprintf(f, "\n]}\n");
@@ -456,6 +515,28 @@ int tune_load_impl(frntt_ctx* ctx, const char* path) {
     check.n_pass = t.n_pass;
     for (int i = 0; i < 4; ++i) check.pass_log[i] = t.pass_log[i];
     if (check_plan_valid(check, l) != FRNTT_OK) return FRNTT_EINVAL;
+    // optional level splits: "levels": [[4, 3, 3], [], ...], one list per pass
+    const size_t next = s.find("{\"log_n\":", pos + 1);
+    const size_t lv = s.find("\"levels\":", pos);
+    if (lv != std::string::npos && lv < next) {
+      size_t i = s.find('[', lv) + 1;
+      for (int pass = 0; pass < t.n_pass; ++pass) {
+        i = s.find('[', i);
+        const size_t end = s.find(']', i);
+        if (i == std::string::npos || end == std::string::npos || (next != std::string::npos && end > next))
+          return FRNTT_EINVAL;
+        int v[3] = {0, 0, 0};
+        const int got = std::sscanf(s.c_str() + i, "[%d, %d, %d", &v[0], &v[1], &v[2]);
+        const int nl = end == i + 1 ? 0 : std::max(got, 0);
+        int sum = 0;
+        for (int j = 0; j < nl; ++j) sum += v[j];
+        if (nl > 0 && sum != t.pass_log[pass]) return FRNTT_EINVAL;
+        t.nlev[pass] = nl;
+        for (int j = 0; j < 3; ++j) t.lev_log[pass][j] = j < nl ? v[j] : 0;
+        i = end + 1;
+      }
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->tuned[l] = t;
     ctx->has_tuned[l] = true;
     ++loaded;

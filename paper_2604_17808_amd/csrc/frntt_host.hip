@@ -43,33 +43,34 @@ static int split_levels(int l, int max_m, int* out) {
   return n;
 }
 
-// Can level m of a pass with 2^log_t staged elements run on MFMA? Each of
-// the 8 waves of a workgroup takes the same number TPW of 32-vector tiles,
-// and TPW * 2^m <= 16 keeps a wave's data fragments in 64 registers.
-bool mfma_level_ok(int m, int log_t) {
-  if (m < 1 || m > 4) return false;
-  const int tpw_log = log_t - m - 5 - 3;
-  return tpw_log >= 0 && tpw_log + m <= 4;
-}
+// Can level m of a pass with 2^log_t staged elements run on MFMA? The
+// matrix form runs on full 4096-element tiles only: each of the 8 waves of a
+// workgroup takes the same number TPW = 2^(4 - m) of 32-vector tiles, so that
+// a wave's data fragments take 64 registers.
+bool mfma_level_ok(int m, int log_t) { return m >= 1 && m <= 4 && log_t == kMaxLogT; }
 
 // Levels of pass p for the MFMA engine: radices of at most 16, as even as
-// possible. Returns false if some level cannot run on MFMA with 2^log_t
-// staged elements (the pass then runs on the butterfly engine).
+// possible, with a plan kernel for the split. Returns false if the pass cannot
+// run on MFMA (a tile below 4096 elements); it then runs on the butterfly
+// engine.
 static bool plan_levels(Plan& plan, int p, int log_t_pass) {
   const int l = plan.pass_log[p];
   int levs[kMaxLevels];
-  // fewest levels first (each costs a carry merge and a twiddle product);
-  // smaller radices when the staged tile has too few vectors for 16
-  int n = 0;
-  bool ok = false;
-  for (int max_m = 4; max_m >= 1 && !ok; --max_m) {
-    n = split_levels(l, max_m, levs);
-    ok = n <= kMaxLevels;
-    for (int i = 0; i < n && ok; ++i) ok = mfma_level_ok(levs[i], log_t_pass);
+  int n = split_levels(l, 4, levs);
+  if (plan.lev_set[p] && log_t_pass == kMaxLogT) {
+    // the requested split, if it covers the pass and has a plan kernel
+    int sum = 0;
+    for (int i = 0; i < plan.nlev[p] && i < 3; ++i) sum += plan.lev_log[p][i];
+    if (plan.nlev[p] >= 1 && plan.nlev[p] <= 3 && sum == l && mfma_plan_kernel(plan.nlev[p], plan.lev_log[p])) {
+      n = plan.nlev[p];
+      for (int i = 0; i < n; ++i) levs[i] = plan.lev_log[p][i];
+    }
   }
-  if (!ok) n = 0;
-  plan.nlev[p] = n;
-  for (int i = 0; i < n; ++i) plan.lev_log[p][i] = levs[i];
+  bool ok = n <= 3;
+  for (int i = 0; i < n && ok; ++i) ok = mfma_level_ok(levs[i], log_t_pass);
+  ok = ok && mfma_plan_kernel(n, levs) != nullptr;
+  plan.nlev[p] = ok ? n : 0;
+  for (int i = 0; i < kMaxLevels; ++i) plan.lev_log[p][i] = ok && i < n ? levs[i] : 0;
   return ok;
 }
 
@@ -99,20 +100,26 @@ int check_plan_valid(const Plan& p, int log_n) {
   return s == log_n ? FRNTT_OK : FRNTT_EINVAL;
 }
 
-Plan plan_for(const frntt_ctx* ctx, int algo, int log_n) {
+static Plan plan_for_locked(const frntt_ctx* ctx, int algo, int log_n) {
   Plan plan;
   if (ctx && ctx->has_override[algo][log_n]) {
     plan = ctx->plan_override[algo][log_n];
   } else if (ctx && ctx->has_tuned[log_n] && ctx->tuned[log_n].algo == algo) {
-    plan.n_pass = ctx->tuned[log_n].n_pass;
-    for (int i = 0; i < 4; ++i) plan.pass_log[i] = ctx->tuned[log_n].pass_log[i];
+    const TuneEntry& t = ctx->tuned[log_n];
+    plan.n_pass = t.n_pass;
+    for (int i = 0; i < 4; ++i) {
+      plan.pass_log[i] = t.pass_log[i];
+      plan.lev_set[i] = t.nlev[i] > 0;
+      plan.nlev[i] = t.nlev[i];
+      for (int j = 0; j < 3; ++j) plan.lev_log[i][j] = t.lev_log[i][j];
+    }
   } else {
     default_pass_split(log_n, &plan.n_pass, plan.pass_log);
   }
   return plan;
 }
 
-int effective_algo(const frntt_ctx* ctx, int log_n, int requested) {
+static int effective_algo_locked(const frntt_ctx* ctx, int log_n, int requested) {
   int a = requested;
   if (a == FRNTT_ALGO_AUTO) a = ctx->algo;
   if (a == FRNTT_ALGO_AUTO) {
@@ -120,6 +127,28 @@ int effective_algo(const frntt_ctx* ctx, int log_n, int requested) {
     else a = FRNTT_ALGO_FOURSTEP_MFMA;
   }
   return a;
+}
+
+Plan plan_for(const frntt_ctx* ctx, int algo, int log_n) {
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  return plan_for_locked(ctx, algo, log_n);
+}
+
+int effective_algo(const frntt_ctx* ctx, int log_n, int requested) {
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  return effective_algo_locked(ctx, log_n, requested);
+}
+
+void resolve_plan(const frntt_ctx* ctx, int algo_req, int log_n, int* algo, Plan* plan) {
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  *algo = effective_algo_locked(ctx, log_n, algo_req);
+  *plan = plan_for_locked(ctx, *algo, log_n);
+}
+
+bool stream_capturing(hipStream_t stream) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &st) != hipSuccess) return false;
+  return st != hipStreamCaptureStatusNone;
 }
 
 size_t scratch_bytes_for(int log_n, int batch, int n_pass) {
@@ -153,19 +182,31 @@ static int pass_log_g(const Plan& plan, int p, int log_n, int batch) {
 }
 
 int build_passes(frntt_ctx* ctx, const Plan& plan_in, int log_n, int batch, int kind, void* data,
-                 void* scratch, std::vector<PassParams>* out, int algo) {
+                 void* scratch, std::vector<PassParams>* out, int algo, bool capturing, bool no_tables) {
+  PassParams pp[4];
+  int n = 0;
+  const int rc = build_passes_into(ctx, plan_in, log_n, batch, kind, data, scratch, pp, &n, algo, capturing,
+                                   no_tables);
+  out->assign(pp, pp + (rc == FRNTT_OK ? n : 0));
+  return rc;
+}
+
+int build_passes_into(frntt_ctx* ctx, const Plan& plan_in, int log_n, int batch, int kind, void* data,
+                      void* scratch, PassParams* out, int* n_out, int algo, bool capturing, bool no_tables) {
   Plan plan = plan_in;
-  out->clear();
+  *n_out = 0;
+  if (plan.n_pass < 1 || plan.n_pass > 4) return FRNTT_EINVAL;
   const int dir = (kind == FRNTT_INV || kind == FRNTT_COSET_INV) ? 1 : 0;
+  const bool scaled = !no_tables && first_pass_scaled(ctx, plan);
   // an inverse transform whose first pass reads a twiddle table takes N^-1
   // from that table, and its last pass skips the N^-1 product
-  const bool fold = dir == 1 && first_pass_scaled(plan);
+  const bool fold = dir == 1 && scaled;
   // a coset transform whose first pass reads a twiddle table takes the
   // per-line part of g^n from that table and the rest from its tail
-  const bool coset_fold = kind == FRNTT_COSET && first_pass_scaled(plan);
+  const bool coset_fold = kind == FRNTT_COSET && scaled;
   // a two-pass coset INTT also takes g^-k of the first pass's output digit
   // from that table and the rest of g^-K from its tail
-  const bool coset_inv_fold = kind == FRNTT_COSET_INV && plan.n_pass == 2 && first_pass_scaled(plan);
+  const bool coset_inv_fold = kind == FRNTT_COSET_INV && plan.n_pass == 2 && scaled;
   const u32x4* first_tw = nullptr;
   int d = 0;
   for (int p = 0; p < plan.n_pass; ++p) {
@@ -201,21 +242,25 @@ int build_passes(frntt_ctx* ctx, const Plan& plan_in, int log_n, int batch, int 
     P.wg_count = lines >> lg;
     P.xcd_remap = 1;
     P.pass_tw = nullptr;
-    if (!last) {
+    if (!last && !no_tables) {
       int rc = FRNTT_OK;
       const int coset = !first ? 0 : coset_fold ? 1 : coset_inv_fold ? 2 : 0;
-      P.pass_tw = pass_table(ctx, dir, l, s, first && fold ? log_n : -1, coset, &rc);
+      P.pass_tw = pass_table(ctx, dir, l, s, first && fold ? log_n : -1, coset, &rc, !capturing);
       if (first) first_tw = P.pass_tw;
       if (rc != FRNTT_OK) return rc;
     }
-    out->push_back(P);
+    out[(*n_out)++] = P;
     d += l;
   }
   return FRNTT_OK;
 }
 
-bool first_pass_scaled(const Plan& plan) {
-  if (plan.n_pass < 2) return false;
+bool pass_tables_on(const frntt_ctx* ctx, int log_r, int log_s) {
+  return !(ctx->flags & FRNTT_SPLIT_TWIDDLES) && log_r + log_s <= kPassTableMaxLog;
+}
+
+bool first_pass_scaled(const frntt_ctx* ctx, const Plan& plan) {
+  if (plan.n_pass < 2 || (ctx->flags & FRNTT_SPLIT_TWIDDLES)) return false;
   int log_n = 0;
   for (int p = 0; p < plan.n_pass; ++p) log_n += plan.pass_log[p];
   return log_n <= kPassTableMaxLog;
@@ -229,13 +274,19 @@ static size_t pass_table_entries(int log_r, int log_s, int coset) {
   return ((size_t)1 << (log_r + log_s)) + (coset == 1 ? ((size_t)1 << log_r) : coset == 2 ? ((size_t)1 << log_s) : 0);
 }
 
-const u32x4* pass_table(frntt_ctx* ctx, int dir, int log_r, int log_s, int scale_log, int coset, int* rc) {
+const u32x4* pass_table(frntt_ctx* ctx, int dir, int log_r, int log_s, int scale_log, int coset, int* rc,
+                        bool may_build) {
   *rc = FRNTT_OK;
-  if (log_r + log_s > kPassTableMaxLog) return nullptr;
+  if (!pass_tables_on(ctx, log_r, log_s)) return nullptr;
   const int key = pass_table_key(dir, log_r, log_s, scale_log, coset);
   std::lock_guard<std::mutex> lk(ctx->tw_mu);
   auto it = ctx->pass_tw.find(key);
   if (it != ctx->pass_tw.end()) return (const u32x4*)it->second;
+  if (!may_build) {
+    // a graph capture must not allocate or synchronise: frntt_prepare first
+    *rc = FRNTT_ESTATE;
+    return nullptr;
+  }
   const size_t bytes = 32 * pass_table_entries(log_r, log_s, coset);
   void* p = nullptr;
   hipError_t e = hipMalloc(&p, bytes);
@@ -266,18 +317,55 @@ const u32x4* pass_table(frntt_ctx* ctx, int dir, int log_r, int log_s, int scale
   return (const u32x4*)p;
 }
 
+std::vector<int> pass_table_keys(frntt_ctx* ctx) {
+  std::lock_guard<std::mutex> lk(ctx->tw_mu);
+  std::vector<int> keys;
+  for (const auto& kv : ctx->pass_tw) keys.push_back(kv.first);
+  return keys;
+}
+
+void release_tuning_tables(frntt_ctx* ctx, const std::vector<int>& before, const Plan& chosen) {
+  // keys of the forward tables of the chosen plan
+  std::vector<int> keep(before);
+  for (int p = 0; p + 1 < chosen.n_pass; ++p) {
+    int s = 0;
+    for (int q = p + 1; q < chosen.n_pass; ++q) s += chosen.pass_log[q];
+    keep.push_back(pass_table_key(0, chosen.pass_log[p], s, -1, 0));
+  }
+  std::vector<std::pair<void*, size_t>> drop;
+  {
+    std::lock_guard<std::mutex> lk(ctx->tw_mu);
+    for (auto it = ctx->pass_tw.begin(); it != ctx->pass_tw.end();) {
+      if (std::find(keep.begin(), keep.end(), it->first) == keep.end()) {
+        const int key = it->first;  // (coset << 26) | ... | (log_r << 8) | log_s
+        drop.push_back({it->second, 32 * pass_table_entries((key >> 8) & 0xff, key & 0xff, key >> 26)});
+        it = ctx->pass_tw.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+  if (drop.empty()) return;
+  // no transform can still be reading them once the device is idle
+  (void)hipDeviceSynchronize();
+  for (const auto& d : drop) {
+    ctx->table_bytes -= d.second;
+    (void)hipFree(d.first);
+  }
+}
+
 size_t pending_pass_table_bytes(frntt_ctx* ctx, const Plan& plan, int kind) {
   const int dir = (kind == FRNTT_INV || kind == FRNTT_COSET_INV) ? 1 : 0;
-  const bool fold = dir == 1 && first_pass_scaled(plan);
-  const bool coset_fold = kind == FRNTT_COSET && first_pass_scaled(plan);
-  const bool coset_inv_fold = kind == FRNTT_COSET_INV && plan.n_pass == 2 && first_pass_scaled(plan);
+  const bool fold = dir == 1 && first_pass_scaled(ctx, plan);
+  const bool coset_fold = kind == FRNTT_COSET && first_pass_scaled(ctx, plan);
+  const bool coset_inv_fold = kind == FRNTT_COSET_INV && plan.n_pass == 2 && first_pass_scaled(ctx, plan);
   size_t bytes = 0;
   std::lock_guard<std::mutex> lk(ctx->tw_mu);
   for (int p = 0; p + 1 < plan.n_pass; ++p) {
     int s = 0;
     for (int q = p + 1; q < plan.n_pass; ++q) s += plan.pass_log[q];
     const int l = plan.pass_log[p];
-    if (l + s > kPassTableMaxLog) continue;
+    if (!pass_tables_on(ctx, l, s)) continue;
     const int scale_log = p == 0 && fold ? l + s : -1;
     const int coset = p != 0 ? 0 : coset_fold ? 1 : coset_inv_fold ? 2 : 0;
     if (!ctx->pass_tw.count(pass_table_key(dir, l, s, scale_log, coset)))
@@ -289,8 +377,10 @@ size_t pending_pass_table_bytes(frntt_ctx* ctx, const Plan& plan, int kind) {
 int get_scratch(frntt_ctx* ctx, hipStream_t stream, size_t bytes, void** out) {
   *out = nullptr;
   if (bytes == 0) return FRNTT_OK;
+  const bool capturing = stream_capturing(stream);
   std::lock_guard<std::mutex> lk(ctx->mu);
   Scratch& s = ctx->scratch[stream];
+  if (s.bytes < bytes && capturing) return FRNTT_ESTATE;  // no allocation inside a capture
   if (s.bytes < bytes) {
     if (s.ptr) {
       // the old buffer may still be in use by work queued on this stream
@@ -313,15 +403,17 @@ int get_scratch(frntt_ctx* ctx, hipStream_t stream, size_t bytes, void** out) {
 }
 
 int launch_passes(frntt_ctx* ctx, const std::vector<PassParams>& passes, int algo, hipStream_t stream) {
-  for (const PassParams& P : passes) {
+  return launch_passes(ctx, passes.data(), (int)passes.size(), algo, stream);
+}
+
+int launch_passes(frntt_ctx* ctx, const PassParams* passes, int n, int algo, hipStream_t stream) {
+  for (int i = 0; i < n; ++i) {
+    const PassParams& P = passes[i];
     if (P.wg_count <= 0) continue;
     (void)algo;
-    MfmaPassKernel plan_k = P.engine == 1 && P.log_t == kMaxLogT ? mfma_plan_kernel(P.nlev, P.lev_log) : nullptr;
+    MfmaPassKernel plan_k = P.engine == 1 ? mfma_plan_kernel(P.nlev, P.lev_log) : nullptr;
     if (plan_k)
       hipLaunchKernelGGL(plan_k, dim3((unsigned)P.wg_count), dim3(kMfmaThreads), 0, stream, P, ctx->tables);
-    else if (P.engine == 1)
-      hipLaunchKernelGGL(ntt_pass_mfma_kernel, dim3((unsigned)P.wg_count), dim3(kMfmaThreads), 0, stream, P,
-                         ctx->tables);
     else
       hipLaunchKernelGGL(ntt_pass_bfly_kernel, dim3((unsigned)P.wg_count), dim3(kBflyThreads), 0, stream, P,
                          ctx->tables);
@@ -354,8 +446,14 @@ int transform_impl(frntt_ctx* ctx, void* data, int log_n, int batch, int kind, i
     if (rc) return rc;
   }
   if (log_n == 0) return FRNTT_OK;  // identity (N^-1 = 1, g^0 = 1)
-  const int algo = effective_algo(ctx, log_n, algo_req);
-  Plan plan = plan_for(ctx, algo, log_n);
+  int algo = 0;
+  Plan plan;
+  resolve_plan(ctx, algo_req, log_n, &algo, &plan);
+  return transform_plan(ctx, data, log_n, batch, kind, algo, plan, stream, workspace, ws_bytes);
+}
+
+int transform_plan(frntt_ctx* ctx, void* data, int log_n, int batch, int kind, int algo, const Plan& plan,
+                   hipStream_t stream, void* workspace, size_t ws_bytes) {
   const size_t need = scratch_bytes_for(log_n, batch, plan.n_pass);
   void* scratch = nullptr;
   if (need) {
@@ -368,7 +466,7 @@ int transform_impl(frntt_ctx* ctx, void* data, int log_n, int batch, int kind, i
     }
   }
   std::vector<PassParams> passes;
-  int rc = build_passes(ctx, plan, log_n, batch, kind, data, scratch, &passes, algo);
+  int rc = build_passes(ctx, plan, log_n, batch, kind, data, scratch, &passes, algo, stream_capturing(stream));
   if (rc) return rc;
   return launch_passes(ctx, passes, algo, stream);
 }
@@ -385,7 +483,7 @@ int frntt_ctx_create(frntt_ctx** out, int hip_device, int max_log_n, unsigned fl
   if (!out) return FRNTT_EINVAL;
   *out = nullptr;
   if (max_log_n < 1 || max_log_n > kMasterLog) return FRNTT_ERANGE;
-  if (flags & ~(unsigned)FRNTT_VALIDATE) return FRNTT_EINVAL;
+  if (flags & ~(unsigned)(FRNTT_VALIDATE | FRNTT_SPLIT_TWIDDLES)) return FRNTT_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev)
     return FRNTT_EINVAL;
@@ -462,16 +560,22 @@ int ntt_coset_inv(frntt_ctx* ctx, void* data, int log_n, int batch, void* stream
 
 int frntt_set_algo(frntt_ctx* ctx, int algo) {
   if (!ctx || algo < FRNTT_ALGO_AUTO || algo > FRNTT_ALGO_FOURSTEP_MFMA) return FRNTT_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
   ctx->algo = algo;
   return FRNTT_OK;
 }
 
-int frntt_get_algo(const frntt_ctx* ctx) { return ctx ? ctx->algo : FRNTT_EINVAL; }
+int frntt_get_algo(const frntt_ctx* ctx) {
+  if (!ctx) return FRNTT_EINVAL;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  return ctx->algo;
+}
 
 int frntt_set_plan(frntt_ctx* ctx, int algo, int log_n, const int* pass_logs, int n_passes) {
   if (!ctx || algo < FRNTT_ALGO_BUTTERFLY || algo > FRNTT_ALGO_FOURSTEP_MFMA) return FRNTT_EINVAL;
   if (log_n < 1 || log_n > kMasterLog) return FRNTT_ERANGE;
   if (n_passes == 0) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->has_override[algo][log_n] = false;
     return FRNTT_OK;
   }
@@ -490,11 +594,28 @@ int frntt_set_plan(frntt_ctx* ctx, int algo, int log_n, const int* pass_logs, in
 int frntt_get_plan(const frntt_ctx* ctx, int algo, int log_n, int* pass_logs, int cap) {
   if (!ctx || algo < FRNTT_ALGO_AUTO || algo > FRNTT_ALGO_FOURSTEP_MFMA) return FRNTT_EINVAL;
   if (log_n < 1 || log_n > kMasterLog) return FRNTT_ERANGE;
-  const int a = effective_algo(ctx, log_n, algo);
-  Plan p = plan_for(ctx, a, log_n);
+  int a = 0;
+  Plan p;
+  resolve_plan(ctx, algo, log_n, &a, &p);
   for (int i = 0; i < p.n_pass && i < cap; ++i)
     if (pass_logs) pass_logs[i] = p.pass_log[i];
   return p.n_pass;
+}
+
+int frntt_get_plan_levels(const frntt_ctx* ctx, int algo, int log_n, int pass, int* levels, int cap) {
+  if (!ctx || algo < FRNTT_ALGO_AUTO || algo > FRNTT_ALGO_FOURSTEP_MFMA) return FRNTT_EINVAL;
+  if (log_n < 1 || log_n > kMasterLog) return FRNTT_ERANGE;
+  int a = 0;
+  Plan p;
+  resolve_plan(ctx, algo, log_n, &a, &p);
+  if (pass < 0 || pass >= p.n_pass) return FRNTT_EINVAL;
+  if (a != FRNTT_ALGO_FOURSTEP_MFMA) return 0;
+  // the levels of a single transform (batch 1) of this size
+  const int lg = pass_log_g(p, pass, log_n, 1);
+  if (!plan_levels(p, pass, p.pass_log[pass] + lg)) return 0;
+  for (int i = 0; i < p.nlev[pass] && i < cap; ++i)
+    if (levels) levels[i] = p.lev_log[pass][i];
+  return p.nlev[pass];
 }
 
 size_t frntt_scratch_bytes(int log_n, int batch) {

@@ -14,7 +14,6 @@
 namespace frntt {
 
 __global__ void ntt_pass_bfly_kernel(PassParams P, DevTables T);
-__global__ void ntt_pass_mfma_kernel(PassParams P, DevTables T);
 
 __global__ void ntt_batch_kernel(BatchParams B, DevTables T);
 __global__ void generate_kernel(u32x4* out, uint64_t seed, uint64_t stream_id, uint64_t start,
@@ -30,6 +29,10 @@ struct Plan {
   int pass_log[4] = {0, 0, 0, 0};
   int nlev[4] = {0, 0, 0, 0};
   int lev_log[4][kMaxLevels] = {};
+  // lev_set[p]: pass p asks for the level split in nlev[p] / lev_log[p] (the
+  // autotuner's choice) instead of the default one; used if a plan kernel
+  // exists for it and the pass runs on the matrix form
+  bool lev_set[4] = {false, false, false, false};
   int log_t = 12;   // elements per workgroup (upper bound)
 };
 
@@ -55,10 +58,18 @@ struct BatchBuffers {
   hipEvent_t event = nullptr;  // recorded after the upload from `host`
 };
 
+// Algorithm and plan fixed for one job of a batch.
+struct JobPlan {
+  int algo = 0;
+  Plan plan;
+};
+
 struct TuneEntry {
   int algo = FRNTT_ALGO_FOURSTEP_MFMA;
   int n_pass = 0;
   int pass_log[4] = {0, 0, 0, 0};
+  int nlev[4] = {0, 0, 0, 0};      // level split per pass (matrix form; 0: default)
+  int lev_log[4][3] = {};
   float ms = 0.f;
 };
 
@@ -68,7 +79,7 @@ struct frntt_ctx {
   int device = 0;
   int max_log_n = 0;
   unsigned flags = 0;
-  int algo = FRNTT_ALGO_AUTO;
+  int algo = FRNTT_ALGO_AUTO;       // guarded by mu
   int cu_count = 0;
   mutable int last_hip_error = 0;
   void* table_mem = nullptr;       // single device allocation holding all tables
@@ -80,7 +91,7 @@ struct frntt_ctx {
   bool has_override[3][29] = {};
   frntt::TuneEntry tuned[29];
   bool has_tuned[29] = {};
-  std::mutex mu;                   // guards scratch, graphs, tuning state
+  mutable std::mutex mu;           // guards algo, plan overrides, tuned plans, scratch, graphs
   std::map<hipStream_t, frntt::Scratch> scratch;
   std::vector<frntt::GraphEntry> graphs;
   std::map<hipStream_t, frntt::BatchBuffers> batch_bufs;
@@ -93,10 +104,28 @@ namespace frntt {
 
 int set_hip_error(const frntt_ctx* ctx, hipError_t e);
 // Default or overridden plan for (algo, log_n); algo must be BUTTERFLY or MFMA.
+// Takes ctx->mu.
 Plan plan_for(const frntt_ctx* ctx, int algo, int log_n);
-// Build the per-pass launch parameters of one transform.
+// The algorithm and plan a call with algorithm `algo_req` uses for this size,
+// read together under ctx->mu.
+void resolve_plan(const frntt_ctx* ctx, int algo_req, int log_n, int* algo, Plan* plan);
+// Is work on `stream` being captured into a graph? Such calls must not
+// allocate or synchronise, so they fail with FRNTT_ESTATE where they would.
+bool stream_capturing(hipStream_t stream);
+// Build the per-pass launch parameters of one transform. A pass-twiddle table
+// that does not exist yet is built (synchronously) unless `capturing`, in
+// which case the call fails with FRNTT_ESTATE.
+// With no_tables every pass twiddle comes from the split tables (no table is
+// looked up or built).
 int build_passes(frntt_ctx* ctx, const Plan& plan, int log_n, int batch, int kind,
-                 void* data, void* scratch, std::vector<PassParams>* out, int algo);
+                 void* data, void* scratch, std::vector<PassParams>* out, int algo, bool capturing = false,
+                 bool no_tables = false);
+// The same into a caller's array of at least 4 entries (no host allocation).
+int build_passes_into(frntt_ctx* ctx, const Plan& plan, int log_n, int batch, int kind, void* data,
+                      void* scratch, PassParams* out, int* n_out, int algo, bool capturing, bool no_tables);
+// One transform with an explicit plan (no plan lookup).
+int transform_plan(frntt_ctx* ctx, void* data, int log_n, int batch, int kind, int algo, const Plan& plan,
+                   hipStream_t stream, void* workspace, size_t ws_bytes);
 // Pass-twiddle table w_(2^(log_r + log_s))^(rest * k) at [k][rest] for a
 // non-last pass, times 2^-scale_log when scale_log >= 0, times g^rest with
 // 2^log_r pre-scale entries (g^(2^log_s))^j appended when coset == 1, times
@@ -107,17 +136,28 @@ int build_passes(frntt_ctx* ctx, const Plan& plan, int log_n, int batch, int kin
 // exceed kPassTableMaxLog entries (the pass then forms each twiddle from the
 // split tables).
 constexpr int kPassTableMaxLog = 25;
-const u32x4* pass_table(frntt_ctx* ctx, int dir, int log_r, int log_s, int scale_log, int coset, int* rc);
+const u32x4* pass_table(frntt_ctx* ctx, int dir, int log_r, int log_s, int scale_log, int coset, int* rc,
+                        bool may_build = true);
+// Does a non-last pass of radix 2^log_r and stride 2^log_s read a twiddle
+// table (no FRNTT_SPLIT_TWIDDLES, at most 2^kPassTableMaxLog entries)?
+bool pass_tables_on(const frntt_ctx* ctx, int log_r, int log_s);
 // Does the first pass of `plan` read a twiddle table (so that an inverse
 // transform can take N^-1 from it)?
-bool first_pass_scaled(const Plan& plan);
+bool first_pass_scaled(const frntt_ctx* ctx, const Plan& plan);
 // Bytes of the pass-twiddle tables a transform with this plan and kind would
 // still have to build.
 size_t pending_pass_table_bytes(frntt_ctx* ctx, const Plan& plan, int kind);
+// Takes ctx->mu.
 int effective_algo(const frntt_ctx* ctx, int log_n, int requested);
+// Keys of the pass-twiddle tables built so far.
+std::vector<int> pass_table_keys(frntt_ctx* ctx);
+// After tuning: free the pass-twiddle tables built since `before` except the
+// forward tables of the chosen plan (waits for the device first).
+void release_tuning_tables(frntt_ctx* ctx, const std::vector<int>& before, const Plan& chosen);
 size_t scratch_bytes_for(int log_n, int batch, int n_pass);
 int get_scratch(frntt_ctx* ctx, hipStream_t stream, size_t bytes, void** out);
 int launch_passes(frntt_ctx* ctx, const std::vector<PassParams>& passes, int algo, hipStream_t stream);
+int launch_passes(frntt_ctx* ctx, const PassParams* passes, int n, int algo, hipStream_t stream);
 bool mfma_level_ok(int m, int log_t);
 int transform_impl(frntt_ctx* ctx, void* data, int log_n, int batch, int kind, int algo,
                    hipStream_t stream, void* workspace, size_t ws_bytes);

@@ -13,6 +13,7 @@
 // independent of what shares its launch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -26,7 +27,8 @@
 
 namespace frntt {
 
-int batch_impl_ws(frntt_ctx* ctx, const frntt_job* jobs, void* const* scratch, int n_jobs, hipStream_t stream);
+int batch_impl_ws(frntt_ctx* ctx, const frntt_job* jobs, void* const* scratch, const JobPlan* plans, int n_jobs,
+                  hipStream_t stream);
 
 namespace {
 
@@ -39,6 +41,8 @@ struct Request {
   uint64_t seed;
   Clock::time_point t_submit;
   Clock::time_point t_done;
+  JobPlan jp;           // algorithm and plan, fixed at submission
+  size_t need = 0;      // data bytes, plus scratch bytes if the plan has several passes
   void* buf = nullptr;  // data, then scratch
   size_t bytes = 0;
   int state = 0;        // 0 queued, 1 admitted, 2 launched, 3 done, 4 released, 5 cancelled
@@ -50,9 +54,10 @@ struct InFlight {
   std::vector<uint64_t> ids;
 };
 
-size_t request_bytes(int log_n) {
-  const size_t data = (size_t)32 << log_n;
-  return log_n > kMaxLogT ? 2 * data : data;
+// Device bytes of a request: its data, and an equal scratch region when its
+// plan has more than one pass (passes alternate between the two).
+size_t request_bytes(int log_n, const Plan& plan) {
+  return ((size_t)32 << log_n) + scratch_bytes_for(log_n, 1, plan.n_pass);
 }
 
 }  // namespace
@@ -74,10 +79,12 @@ struct frntt_server {
   std::deque<uint64_t> queue;        // submitted, not admitted
   std::deque<uint64_t> admitted;     // admitted, not launched
   std::unordered_map<uint64_t, frntt::Request> reqs;
-  std::map<int, std::vector<void*>> free_bufs;  // pool by log_n
+  std::map<size_t, std::vector<void*>> free_bufs;  // pool by buffer size
   std::vector<frntt::InFlight> inflight;
   uint64_t next_id = 1;
   uint64_t completed = 0, batches = 0;
+  uint64_t inflight_requests = 0;    // launched, not yet complete
+  uint64_t peak_inflight_batches = 0, peak_inflight_requests = 0;
   uint64_t outstanding = 0;          // submitted and not done
   bool release_on_done = false;      // recycle buffers as soon as a request completes
   bool stalled = false;              // queue head cannot be admitted and nothing runs
@@ -93,9 +100,9 @@ namespace {
 // Take a buffer for `log_n` from the pool (allocating if needed) while the
 // budget allows; called with the lock held.
 bool take_buffer(frntt_server* s, Request& r) {
-  const size_t need = request_bytes(r.log_n);
+  const size_t need = r.need;
   if (s->in_use + need + s->ctx->table_bytes > s->budget) return false;
-  auto& fl = s->free_bufs[r.log_n];
+  auto& fl = s->free_bufs[need];
   void* p = nullptr;
   if (!fl.empty()) {
     p = fl.back();
@@ -108,7 +115,7 @@ bool take_buffer(frntt_server* s, Request& r) {
         if (!kv.second.empty()) {
           hipFree(kv.second.back());
           kv.second.pop_back();
-          s->pool_bytes -= request_bytes(kv.first);
+          s->pool_bytes -= kv.first;
           freed = true;
           break;
         }
@@ -126,7 +133,7 @@ bool take_buffer(frntt_server* s, Request& r) {
 
 void give_back(frntt_server* s, Request& r) {
   if (!r.buf) return;
-  s->free_bufs[r.log_n].push_back(r.buf);
+  s->free_bufs[r.bytes].push_back(r.buf);
   s->in_use -= r.bytes;
   r.buf = nullptr;
   r.bytes = 0;
@@ -154,6 +161,7 @@ void worker_main(frntt_server* s) {
     if (slot >= 0 && !s->admitted.empty()) {
       std::vector<frntt_job> jobs;
       std::vector<void*> scratch;
+      std::vector<JobPlan> plans;
       std::vector<uint64_t> ids;
       hipStream_t st = s->streams[(size_t)slot];
       while (!s->admitted.empty()) {
@@ -162,12 +170,14 @@ void worker_main(frntt_server* s) {
         const uint64_t n = 1ull << r.log_n;
         frntt_generate(s->ctx, r.buf, r.seed, r.id, 0, n, st);
         jobs.push_back({r.buf, r.log_n, r.kind});
-        scratch.push_back(r.log_n > kMaxLogT ? (uint8_t*)r.buf + ((size_t)32 << r.log_n) : nullptr);
+        const size_t data = (size_t)32 << r.log_n;
+        scratch.push_back(r.need > data ? (uint8_t*)r.buf + data : nullptr);
+        plans.push_back(r.jp);
         ids.push_back(r.id);
         r.state = 2;
       }
       lk.unlock();
-      int rc = batch_impl_ws(s->ctx, jobs.data(), scratch.data(), (int)jobs.size(), st);
+      int rc = batch_impl_ws(s->ctx, jobs.data(), scratch.data(), plans.data(), (int)jobs.size(), st);
       hipEvent_t ev = nullptr;
       if (rc == FRNTT_OK && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) rc = FRNTT_EHIP;
       if (rc == FRNTT_OK && hipEventRecord(ev, st) != hipSuccess) rc = FRNTT_EHIP;
@@ -186,6 +196,9 @@ void worker_main(frntt_server* s) {
         s->slot_busy[(size_t)slot] = true;
         s->inflight.push_back({slot, ev, ids});
         ++s->batches;
+        s->inflight_requests += ids.size();
+        s->peak_inflight_batches = std::max<uint64_t>(s->peak_inflight_batches, s->inflight.size());
+        s->peak_inflight_requests = std::max(s->peak_inflight_requests, s->inflight_requests);
       }
       continue;
     }
@@ -204,6 +217,7 @@ void worker_main(frntt_server* s) {
           if (s->release_on_done) give_back(s, r);
         }
         hipEventDestroy(f.event);
+        s->inflight_requests -= f.ids.size();
         s->slot_busy[(size_t)f.slot] = false;
         s->inflight.erase(s->inflight.begin() + (long)i);
         any = true;
@@ -279,26 +293,30 @@ int frntt_server_create(frntt_server** out, frntt_ctx* ctx, size_t hbm_budget_by
 int frntt_server_submit(frntt_server* s, int kind, int log_n, uint64_t data_seed, uint64_t* ticket) {
   if (!s || !ticket || kind < FRNTT_FWD || kind > FRNTT_COSET_INV) return FRNTT_EINVAL;
   if (log_n < 1 || log_n > s->ctx->max_log_n) return FRNTT_ERANGE;
+  // the algorithm and plan are fixed now; the buffer is sized for them
+  frntt::JobPlan jp;
+  frntt::resolve_plan(s->ctx, FRNTT_ALGO_AUTO, log_n, &jp.algo, &jp.plan);
+  const size_t need = request_bytes(log_n, jp.plan);
   {
     // the pass-twiddle tables this request will use count against the
     // budget from the start: a request that could never fit is refused
     // before anything is built; otherwise they are built now (once per size
     // and direction)
-    const int algo = frntt::effective_algo(s->ctx, log_n, FRNTT_ALGO_AUTO);
-    const frntt::Plan plan = frntt::plan_for(s->ctx, algo, log_n);
-    const size_t extra = frntt::pending_pass_table_bytes(s->ctx, plan, kind);
-    if (request_bytes(log_n) + s->ctx->table_bytes + extra > s->budget) return FRNTT_EBUSY;
+    const size_t extra = frntt::pending_pass_table_bytes(s->ctx, jp.plan, kind);
+    if (need + s->ctx->table_bytes + extra > s->budget) return FRNTT_EBUSY;
     std::vector<frntt::PassParams> tmp;
-    const int rc = frntt::build_passes(s->ctx, plan, log_n, 1, kind, nullptr, nullptr, &tmp, algo);
+    const int rc = frntt::build_passes(s->ctx, jp.plan, log_n, 1, kind, nullptr, nullptr, &tmp, jp.algo);
     if (rc != FRNTT_OK) return rc;
   }
-  if (request_bytes(log_n) + s->ctx->table_bytes > s->budget) return FRNTT_EBUSY;
+  if (need + s->ctx->table_bytes > s->budget) return FRNTT_EBUSY;
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->stop) return FRNTT_ESTATE;
   Request r;
   r.id = s->next_id++;
   r.kind = kind;
   r.log_n = log_n;
+  r.jp = jp;
+  r.need = need;
   r.seed = data_seed;
   r.t_submit = Clock::now();
   s->reqs[r.id] = r;
@@ -377,6 +395,14 @@ int frntt_server_stats(frntt_server* s, uint64_t* completed, uint64_t* batches, 
   if (completed) *completed = s->completed;
   if (batches) *batches = s->batches;
   if (peak_bytes) *peak_bytes = s->peak + s->ctx->table_bytes;
+  return FRNTT_OK;
+}
+
+int frntt_server_peak_inflight(frntt_server* s, uint64_t* batches, uint64_t* requests) {
+  if (!s) return FRNTT_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (batches) *batches = s->peak_inflight_batches;
+  if (requests) *requests = s->peak_inflight_requests;
   return FRNTT_OK;
 }
 

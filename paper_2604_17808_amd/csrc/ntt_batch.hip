@@ -5,33 +5,39 @@
 
 namespace frntt {
 
-// One (pass, workgroup) item. A matrix-form pass with a full 4096-element
-// tile runs the level code specialised to its level split (the same bodies
-// as the plan kernels of single transforms); other passes take the generic
-// per-pass path.
-static_assert(PassPlan<4, 4, 4>::kLds <= kPlanBatLds && PassPlan<4, 4, 3>::kLds <= kPlanBatLds &&
-                  PassPlan<4, 3, 3>::kLds <= kPlanBatLds && PassPlan<3, 3, 3>::kLds <= kPlanBatLds &&
-                  PassPlan<4, 4, 0>::kLds <= kPlanBatLds && PassPlan<4, 3, 0>::kLds <= kPlanBatLds &&
-                  PassPlan<3, 3, 0>::kLds <= kPlanBatLds && PassPlan<3, 2, 0>::kLds <= kPlanBatLds,
-              "the batch kernel's constant-block area holds every plan's blocks");
+// One (pass, workgroup) item. A matrix-form pass (always a full
+// 4096-element tile) runs the level code specialised to its level split (the
+// same bodies as the plan kernels of single transforms); a butterfly-form pass
+// runs the butterfly stages with this kernel's 512 threads.
+#define FRNTT_BATCH_LDS_OK(a, b, c) static_assert(PassPlan<a, b, c>::kLds <= kPlanBatLds, "plan blocks fit");
+FRNTT_PLAN_KERNELS(FRNTT_BATCH_LDS_OK)
+#undef FRNTT_BATCH_LDS_OK
+
+// Each plan body is a function of its own (not inlined into the persistent
+// loop), so that its registers are allocated for it alone.
+template <int M0, int M1, int M2>
+__device__ __attribute__((noinline)) void batch_plan_pass(u32x4* lds, i32x4* lds_f, const PassParams& P,
+                                                          const DevTables& T, int64_t wg) {
+  run_pass_plan<M0, M1, M2>(lds, lds_f, P, T, wg);
+}
+
+__device__ __attribute__((noinline)) void batch_bfly_pass(u32x4* lds, const PassParams& P, const DevTables& T,
+                                                          int64_t wg) {
+  run_pass_bfly<kMfmaThreads>(lds, P, T, wg);
+}
 
 __device__ FRNTT_INLINE void run_batch_pass(u32x4* lds, i32x4* lds_f, const PassParams& P, const DevTables& T,
                                             int64_t wg) {
   const int nlev = P.nlev;
   const int code = __builtin_amdgcn_readfirstlane(
-      P.engine == 1 && P.log_t == kMaxLogT
-          ? nlev * 1000 + P.lev_log[0] * 100 + (nlev > 1 ? P.lev_log[1] : 0) * 10 + (nlev > 2 ? P.lev_log[2] : 0)
-          : 0);
+      P.engine == 1 ? nlev * 1000 + P.lev_log[0] * 100 + (nlev > 1 ? P.lev_log[1] : 0) * 10 + (nlev > 2 ? P.lev_log[2] : 0)
+                    : 0);
   switch (code) {
-    case 3444: run_pass_plan<4, 4, 4>(lds, lds_f, P, T, wg); return;
-    case 3443: run_pass_plan<4, 4, 3>(lds, lds_f, P, T, wg); return;
-    case 3433: run_pass_plan<4, 3, 3>(lds, lds_f, P, T, wg); return;
-    case 3333: run_pass_plan<3, 3, 3>(lds, lds_f, P, T, wg); return;
-    case 2440: run_pass_plan<4, 4, 0>(lds, lds_f, P, T, wg); return;
-    case 2430: run_pass_plan<4, 3, 0>(lds, lds_f, P, T, wg); return;
-    case 2330: run_pass_plan<3, 3, 0>(lds, lds_f, P, T, wg); return;
-    case 2320: run_pass_plan<3, 2, 0>(lds, lds_f, P, T, wg); return;
-    default: run_pass<2, kMfmaThreads>(lds, lds_f, P, T, wg);
+#define FRNTT_BATCH_CASE(a, b, c) \
+    case (c > 0 ? 3 : b > 0 ? 2 : 1) * 1000 + a * 100 + b * 10 + c: batch_plan_pass<a, b, c>(lds, lds_f, P, T, wg); return;
+    FRNTT_PLAN_KERNELS(FRNTT_BATCH_CASE)
+#undef FRNTT_BATCH_CASE
+    default: batch_bfly_pass(lds, P, T, wg);
   }
 }
 

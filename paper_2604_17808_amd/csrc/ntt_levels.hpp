@@ -8,17 +8,22 @@
 // back to HBM.
 //
 // The sub-DFT of a line runs on one of two engines:
-//   * butterfly: radix-2 decimation-in-frequency stages in LDS with
-//     Montgomery twiddle products on the VALUs (the paper's butterfly NTT);
+//   * butterfly: radix-4 (and one radix-2) decimation-in-frequency stages in
+//     LDS with Montgomery twiddle products on the VALUs (the paper's
+//     butterfly NTT);
 //   * MFMA: nested levels of radix rho <= 16. Level l reads LDS row n_l (its
 //     input digit) across V = T / rho vectors; the rho-point DFT of 32
 //     vectors at a time is a GEMM of the BAT byte-limb constant blocks
 //     E[(k,h),(n,a)] (signed digit h of w^(kn) * 2^(8a) mod r) with the data
-//     bytes on int8 MFMA (Alg. 1's ByteDecompose and einsum), followed by the
-//     carry merge sum_h P_h 2^(8h) and reduction mod r (ByteMerge and the
-//     final correction), a write into the row order the next level reads,
-//     and then, as an elementwise phase over the tile, the inter-level
-//     twiddle. The vector index is always the fastest LDS index.
+//     bytes on int8 MFMA (Alg. 1's ByteDecompose and einsum). Outputs come in
+//     pairs (k', k' + rho/2): the even-digit and odd-digit sums e, o of
+//     w^(k' n) x_n take rho MFMAs, and e + o, e - o are the two outputs
+//     (w^((k' + rho/2) n) = (-1)^n w^(k' n)), so a radix-rho level costs
+//     rho^2 / 2 MFMAs per 32 vectors. Then the carry merge
+//     sum_h P_h 2^(8h) and reduction mod r (ByteMerge and the final
+//     correction), the inter-level twiddle, and a write into the row order
+//     the next level reads. The vector work of one pair runs between the
+//     MFMAs of the next.
 // Both engines compute exact field values, so results are bit-identical.
 #pragma once
 #include "ntt_device.hpp"
@@ -123,16 +128,30 @@ __device__ FRNTT_INLINE void store_lines(const u32x4* lds, const PassParams& P, 
 
 // ------------------------------------------------------- butterfly engine
 
-// log_r radix-2 DIF stages over every line, in place in LDS; afterwards row i
-// of a line holds output bitrev(i).
+// Radix-2 and radix-4 decimation-in-frequency stages over every line, in
+// place in LDS; afterwards row i of a line holds output bitrev(i).
+//
+// A radix-4 stage is two radix-2 DIF stages fused. With quarter span q,
+// w = w_(4q) and j = i mod q, the inputs a, b, c, d at rows i, i + q,
+// i + 2q, i + 3q become
+//   t0 = a + c, t1 = a - c, t2 = b + d, t3 = (b - d) w_4,
+//   row i: t0 + t2,            row i + q:  (t0 - t2) w^(2j),
+//   row i + 2q: (t1 + t3) w^j, row i + 3q: (t1 - t3) w^(3j),
+// which is what the two radix-2 stages leave in those rows (w^(j+q) =
+// w^j w_4 and w_(2q)^j = w^(2j)). One product by w_4 and three twiddle
+// products per four elements, the same count as two radix-2 stages, but half
+// the LDS round trips and barriers; in the last stage (q = 1, j = 0) the
+// three twiddles are 1 and are skipped. An odd log_r starts with one radix-2
+// stage.
 template <int NT>
 __device__ FRNTT_INLINE void bfly_stages(u32x4* lds, const PassParams& P, const DevTables& T) {
-  const int half_el = 1 << (P.log_t - 1);
   const int G = 1 << P.log_g;
   const int tid = threadIdx.x;
   const u32x4* w = T.w4096[P.dir];
-  for (int s = 0; s < P.log_r; ++s) {
-    const int log_span = P.log_r - 1 - s;
+  int left = P.log_r;  // log2 span of the blocks still to split
+  if (left & 1) {
+    const int half_el = 1 << (P.log_t - 1);
+    const int log_span = left - 1;
     const int span = 1 << log_span;
 #pragma unroll 1
     for (int b = tid; b < half_el; b += NT) {
@@ -143,9 +162,39 @@ __device__ FRNTT_INLINE void bfly_stages(u32x4* lds, const PassParams& P, const 
       const int e0 = i0 * G + line, e1 = (i0 + span) * G + line;
       const fr_t u = lds_ld(lds, e0), v = lds_ld(lds, e1);
       lds_st(lds, e0, fr_add(u, v));
-      // w_{2 span}^j = w_4096^(j * 2^s * 2^(12 - log_r))
-      const fr_t tw = ld_elem(w, (j << s) << (12 - P.log_r));
+      // w_(2 span)^j = w_4096^(j * 4096 / (2 span))
+      const fr_t tw = ld_elem(w, j << (12 - log_span - 1));
       lds_st(lds, e1, mont_mul(fr_sub(u, v), tw));
+    }
+    __syncthreads();
+    left -= 1;
+  }
+  const fr_t w4 = ld_elem(w, 1024);  // w_4 = w_4096^1024
+  const int quarter_el = 1 << (P.log_t - 2);
+  for (; left >= 2; left -= 2) {
+    const int log_q = left - 2;
+    const int q = 1 << log_q;
+    const int tw_shift = 12 - log_q - 2;  // w_(4q)^e = w_4096^(e << tw_shift)
+#pragma unroll 1
+    for (int b = tid; b < quarter_el; b += NT) {
+      const int line = b & (G - 1);
+      const int bb = b >> P.log_g;             // radix-4 butterfly index inside the line
+      const int j = bb & (q - 1);
+      const int i0 = ((bb >> log_q) << (log_q + 2)) + j;
+      const int e0 = i0 * G + line, e1 = e0 + q * G, e2 = e1 + q * G, e3 = e2 + q * G;
+      const fr_t a = lds_ld(lds, e0), bq = lds_ld(lds, e1), c = lds_ld(lds, e2), d = lds_ld(lds, e3);
+      const fr_t t0 = fr_add(a, c), t1 = fr_sub(a, c), t2 = fr_add(bq, d);
+      const fr_t t3 = mont_mul(fr_sub(bq, d), w4);
+      lds_st(lds, e0, fr_add(t0, t2));
+      if (log_q == 0) {
+        lds_st(lds, e1, fr_sub(t0, t2));
+        lds_st(lds, e2, fr_add(t1, t3));
+        lds_st(lds, e3, fr_sub(t1, t3));
+      } else {
+        lds_st(lds, e1, mont_mul(fr_sub(t0, t2), ld_elem(w, ((2 * j) << tw_shift) & 4095)));
+        lds_st(lds, e2, mont_mul(fr_add(t1, t3), ld_elem(w, (j << tw_shift) & 4095)));
+        lds_st(lds, e3, mont_mul(fr_sub(t1, t3), ld_elem(w, ((3 * j) << tw_shift) & 4095)));
+      }
     }
     __syncthreads();
   }
@@ -293,7 +342,7 @@ constexpr int bat_lds_size() { return (1 << M) * 72; }  // i32x4 units
 //   KIND 0: nothing (last level of a forward or coset transform: the store
 //           reduces y < 3r),
 //   KIND 1: the inter-level twiddle w^(nn k) of the size-2^(m + q_log)
-//           sub-problem (one Montgomery product),
+//           sub-problem (one Montgomery product, output left below 2r),
 //   KIND 2: the pass twiddle w^(rest k) of the size-2^(l + S) sub-problem
 //           (last level of a non-last pass; the twiddle is the product of two
 //           table entries: two Montgomery products),
@@ -311,11 +360,14 @@ struct PairWork {
   fr_t tw, tw2, tw3;  // factors (Montgomery form), loaded when the pair starts
   fr_t y;             // the output of the pair: below 3r for KIND 0, canonical otherwise
 
-  // step Q of a Montgomery product a * b -> out (11 steps)
-  template <int Q>
+  // step Q of a Montgomery product a * b -> out (11 steps); a LAZY product
+  // leaves its output below 2r (the inter-level twiddle: the next level reads
+  // only its 32 bytes)
+  template <int Q, bool LAZY = false>
   __device__ FRNTT_INLINE void prod(const fr_t& a, const fr_t& b, fr_t& out) {
     if constexpr (Q == 0) mm.load(a, b);
     else if constexpr (Q <= 9) mm.row(Q - 1);
+    else if constexpr (LAZY) out = mm.finish_lazy();
     else out = mm.finish();
   }
   template <int S>
@@ -324,7 +376,9 @@ struct PairWork {
     if constexpr (S < P0) {
       mg.template step<S>();
       if constexpr (S == P0 - 1) y = mg.result();
-    } else if constexpr (KIND == 1 || KIND == 3 || KIND == 5 || KIND == 7) {
+    } else if constexpr (KIND == 1) {
+      prod<S - P0, true>(tw, y, y);
+    } else if constexpr (KIND == 3 || KIND == 5 || KIND == 7) {
       prod<S - P0>(tw, y, y);
     } else if constexpr (KIND == 2 || KIND == 6) {
       if constexpr (S < P1) prod<S - P0>(tw, tw2, tw);
@@ -345,42 +399,41 @@ struct PairWork {
   }
 };
 
-// One pipelined step of an MFMA level: issue the 2 x RHO MFMAs of the pair
-// (k0, k0 + 1) of one tile into (n0, n1), seeded with the signed-digit
-// correction and the row offsets, while the work `wk` on the previous pair
-// (if WORKING) advances through its steps, spread evenly over the MFMA issue
-// slots. The constant blocks (E depends on k n mod RHO only) are read from
-// LDS one digit ahead; a scheduling barrier after each digit keeps the
-// vector work between the MFMAs, so the matrix and vector pipes of a SIMD
-// overlap within the wave.
+// One pipelined output pair (k', k' + RHO/2) of a tile: the RHO MFMAs of
+// digits n = 0..RHO-1 accumulate into e (n even) and o (n odd) with the
+// blocks of k' n mod RHO, then n0 = e + o holds output k' and n1 = e - o
+// output k' + RHO/2 (w^((k' + RHO/2) n) = (-1)^n w^(k' n)). The work `wk` on
+// the previous pair (if WORKING) advances through its steps, spread evenly
+// over the MFMA issue slots; the constant blocks are read from LDS one digit
+// ahead, and a scheduling barrier after each digit keeps the vector work
+// between the MFMAs, so the matrix and vector pipes of a SIMD overlap.
 template <int RHO, bool WORKING, class W, int N>
 struct DigitLoop {
   __device__ FRNTT_INLINE static void run(const i32x4* lds_f, const i32x4 (&Bt)[RHO], int k0, int lane,
-                                          i32x16& n0, i32x16& n1, W& wk, i32x4 a0, i32x4 a1) {
+                                          i32x16& e, i32x16& o, W& wk, i32x4 a) {
     if constexpr (N < RHO) {
-      constexpr int SLOTS = 2 * RHO;
-      i32x4 p0 = a0, p1 = a1;
-      if constexpr (N + 1 < RHO) {
-        p0 = lds_f[((k0 * (N + 1)) & (RHO - 1)) * 64 + lane];
-        p1 = lds_f[(((k0 + 1) * (N + 1)) & (RHO - 1)) * 64 + lane];
-      }
-      n0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, Bt[N], n0, 0, 0, 0);
-      if constexpr (WORKING) wk.template steps<(2 * N) * W::kSteps / SLOTS, (2 * N + 1) * W::kSteps / SLOTS>();
-      n1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, Bt[N], n1, 0, 0, 0);
-      if constexpr (WORKING) wk.template steps<(2 * N + 1) * W::kSteps / SLOTS, (2 * N + 2) * W::kSteps / SLOTS>();
+      i32x4 p = a;
+      if constexpr (N + 1 < RHO) p = lds_f[((k0 * (N + 1)) & (RHO - 1)) * 64 + lane];
+      if constexpr (N & 1) o = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, Bt[N], o, 0, 0, 0);
+      else e = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, Bt[N], e, 0, 0, 0);
+      if constexpr (WORKING) wk.template steps<N * W::kSteps / RHO, (N + 1) * W::kSteps / RHO>();
       __builtin_amdgcn_sched_barrier(0);
-      DigitLoop<RHO, WORKING, W, N + 1>::run(lds_f, Bt, k0, lane, n0, n1, wk, p0, p1);
+      DigitLoop<RHO, WORKING, W, N + 1>::run(lds_f, Bt, k0, lane, e, o, wk, p);
     }
   }
 };
 
+// Seeds of the pair's even and odd accumulators: the signed-digit correction
+// of their digits and, on the even one only, the row offsets.
 template <int RHO, bool WORKING, class W>
 __device__ FRNTT_INLINE void mfma_pair_work(const i32x4* lds_f, const i32x4* init, const i32x4 (&Bt)[RHO], int k0,
                                             int lane, int half, i32x16& n0, i32x16& n1, W& wk) {
-  n0 = load_init(init, k0, half);
-  n1 = load_init(init, k0 + 1, half);
-  const i32x4 a = lds_f[lane];  // k * 0 = 0
-  DigitLoop<RHO, WORKING, W, 0>::run(lds_f, Bt, k0, lane, n0, n1, wk, a, a);
+  i32x16 e = load_init(init, 2 * k0, half);
+  i32x16 o = load_init(init, 2 * k0 + 1, half);
+  const i32x4 a = lds_f[lane];  // k' * 0 = 0
+  DigitLoop<RHO, WORKING, W, 0>::run(lds_f, Bt, k0, lane, e, o, wk, a);
+  n0 = e + o;
+  n1 = e - o;
 }
 
 // The output pairs of tile T of a wave (tiles unrolled at compile time, so
@@ -406,7 +459,7 @@ struct TileLoop {
       const int64_t rest = mp.rest;
 #pragma unroll 1
       for (int kp = 0; kp < NKP; ++kp) {
-        const int k = 2 * kp + half;  // this lane's output digit
+        const int k = kp + half * NKP;  // this lane's output digit: pair kp holds kp and kp + RHO/2
         wk.mg.a0 = n0;
         wk.mg.a1 = n1;
         if (KIND == 1) wk.tw = small_tw(Tb, P.dir, g.m + g.q_log, (uint32_t)(nn * k));
@@ -426,7 +479,7 @@ struct TileLoop {
           if (KIND == 4) wk.tw3 = ld_elem(Tb.ninv, P.log_n);
         }
         if (kp + 1 < NKP) {
-          mfma_pair_work<RHO, true>(lds_f, init, B[T], 2 * kp + 2, lane, half, n0, n1, wk);
+          mfma_pair_work<RHO, true>(lds_f, init, B[T], kp + 1, lane, half, n0, n1, wk);
         } else if constexpr (T + 1 < TPW) {
           mfma_pair_work<RHO, true>(lds_f, init, B[T + 1], 0, lane, half, n0, n1, wk);
         } else {
@@ -484,94 +537,23 @@ __device__ FRNTT_INLINE void mfma_level(u32x4* lds, i32x4* blk, const PassParams
   __syncthreads();
 }
 
-template <int M, int TPW>
-__device__ FRNTT_INLINE void mfma_level_any(u32x4* lds, i32x4* blk, const PassParams& P, const DevTables& T,
-                                            const LevelGeom& g, int64_t wg) {
-  if (!g.last) mfma_level<M, TPW, 1>(lds, blk, P, T, g, false, wg);
-  else if (!P.is_last && P.pass_tw) mfma_level<M, TPW, 5>(lds, blk, P, T, g, false, wg);
-  else if (!P.is_last) mfma_level<M, TPW, 2>(lds, blk, P, T, g, false, wg);
-  else if (P.post == 1) mfma_level<M, TPW, 3>(lds, blk, P, T, g, false, wg);
-  else if (P.post == 2) mfma_level<M, TPW, 4>(lds, blk, P, T, g, false, wg);
-  else if (P.post == 3) mfma_level<M, TPW, 6>(lds, blk, P, T, g, false, wg);
-  else if (P.post == 4) mfma_level<M, TPW, 7>(lds, blk, P, T, g, false, wg);
-  else mfma_level<M, TPW, 0>(lds, blk, P, T, g, false, wg);
-}
-
-// Level shapes: 2^(log_t - m - 5) tiles of 32 vectors, TPW = tiles / 8 per
-// wave (the host admits only levels with at least 8 tiles and TPW * RHO <= 16,
-// so a wave's data fragments take at most 64 registers).
-__device__ FRNTT_INLINE void run_mfma_level(u32x4* lds, i32x4* lds_f, const PassParams& P, const DevTables& T,
-                                            const LevelGeom& g, int64_t wg) {
-  const int tpw = 1 << (P.log_t - g.m - 5 - 3);
-  switch (g.m * 16 + tpw) {
-    case 1 * 16 + 8: mfma_level_any<1, 8>(lds, lds_f, P, T, g, wg); break;
-    case 1 * 16 + 4: mfma_level_any<1, 4>(lds, lds_f, P, T, g, wg); break;
-    case 1 * 16 + 2: mfma_level_any<1, 2>(lds, lds_f, P, T, g, wg); break;
-    case 1 * 16 + 1: mfma_level_any<1, 1>(lds, lds_f, P, T, g, wg); break;
-    case 2 * 16 + 4: mfma_level_any<2, 4>(lds, lds_f, P, T, g, wg); break;
-    case 2 * 16 + 2: mfma_level_any<2, 2>(lds, lds_f, P, T, g, wg); break;
-    case 2 * 16 + 1: mfma_level_any<2, 1>(lds, lds_f, P, T, g, wg); break;
-    case 3 * 16 + 2: mfma_level_any<3, 2>(lds, lds_f, P, T, g, wg); break;
-    case 3 * 16 + 1: mfma_level_any<3, 1>(lds, lds_f, P, T, g, wg); break;
-    case 4 * 16 + 1: mfma_level_any<4, 1>(lds, lds_f, P, T, g, wg); break;
-    default: break;  // the host only builds supported level shapes
-  }
-}
-
-// Constant blocks and seeds of the (at most two) distinct level radices of a
-// pass, staged once per pass: the first level's radix at 0, the other one
-// after it. Runs before the tile's loads so that both overlap.
-__device__ FRNTT_INLINE int pass_bat_offset(const PassParams& P, int m) {
-  return m == P.lev_log[0] ? 0 : (1 << P.lev_log[0]) * 72;
-}
-
-template <int NT>
-__device__ FRNTT_INLINE void stage_pass_bats(i32x4* lds_f, const PassParams& P, const DevTables& T) {
-  for (int lev = 0; lev < P.nlev; ++lev) {
-    const int m = P.lev_log[lev];
-    if (lev > 0 && (m == P.lev_log[0] || m == P.lev_log[lev - 1])) continue;
-    const int rho = 1 << m;
-    i32x4* dst = lds_f + pass_bat_offset(P, m);
-    const i32x4* bat = T.bat[P.dir][m];
-    const i32x4* seeds = T.bat_init[P.dir][m];
-    for (int i = threadIdx.x; i < rho * 64; i += NT) dst[i] = bat[i];
-    for (int i = threadIdx.x; i < rho * 8; i += NT) dst[rho * 64 + i] = seeds[i];
-  }
-}
-
-__device__ FRNTT_INLINE void mfma_levels(u32x4* lds, i32x4* lds_f, const PassParams& P, const DevTables& T,
-                                         int64_t wg) {
-  int pprev = 0;
-  int rest = P.log_r;
-  for (int lev = 0; lev < P.nlev; ++lev) {
-    LevelGeom g;
-    g.m = P.lev_log[lev];
-    rest -= g.m;
-    g.pprev_log = pprev;
-    g.q_log = rest;
-    g.next_m = lev + 1 < P.nlev ? P.lev_log[lev + 1] : 0;
-    g.last = lev + 1 == P.nlev;
-    run_mfma_level(lds, lds_f + pass_bat_offset(P, g.m), P, T, g, wg);
-    pprev += g.m;
-  }
-}
-
-// A pass whose levels are known at compile time (radices 2^M0, 2^M1 and,
-// if M2 > 0, 2^M2, staged tile of 4096 elements): the constant blocks of
-// its (at most two) distinct radices are staged once, together with the
-// tile's HBM loads, and every level shape is fixed.
+// A pass of the matrix form (staged tile of 4096 elements) whose levels are
+// known at compile time: radices 2^M0, then 2^M1 if M1 > 0, then 2^M2 if
+// M2 > 0. The constant blocks of its (at most two) distinct radices are staged
+// once, together with the tile's HBM loads, and every level shape is fixed.
 template <int M0, int M1, int M2>
 struct PassPlan {
-  static constexpr int kLevels = M2 > 0 ? 3 : 2;
-  static_assert(M1 == M0 || M2 == 0 || M2 == M0 || M2 == M1, "at most two distinct radices");
+  static constexpr int kLevels = M2 > 0 ? 3 : M1 > 0 ? 2 : 1;
+  static_assert(M1 > 0 || M2 == 0, "levels are given in order");
+  static_assert(M1 == 0 || M1 == M0 || M2 == 0 || M2 == M0 || M2 == M1, "at most two distinct radices");
   // LDS offsets of the blocks of each level: the first radix at 0, the
   // other distinct radix (M1, or M2 when M1 == M0) after it
-  static constexpr int kOff1 = M1 == M0 ? 0 : bat_lds_size<M0>();
+  static constexpr int kOff1 = M1 == M0 || M1 == 0 ? 0 : bat_lds_size<M0>();
   static constexpr int kOff2 = M2 == M0 ? 0 : (M2 == M1 ? kOff1 : bat_lds_size<M0>());
-  static constexpr bool kStage1 = M1 != M0;
+  static constexpr bool kStage1 = M1 > 0 && M1 != M0;
   static constexpr bool kStage2 = M2 > 0 && M2 != M0 && M2 != M1;
-  static constexpr int kLds = bat_lds_size<M0>() + (M1 == M0 ? 0 : bat_lds_size<M1>()) +
-                              (M2 > 0 && M2 != M0 && M2 != M1 ? bat_lds_size<M2>() : 0);
+  static constexpr int kLds = bat_lds_size<M0>() + (kStage1 ? bat_lds_size<(M1 > 0 ? M1 : 1)>() : 0) +
+                              (kStage2 ? bat_lds_size<(M2 > 0 ? M2 : 1)>() : 0);
 };
 constexpr int kPlanBatLds = bat_lds_size<4>() + bat_lds_size<3>();
 
@@ -606,33 +588,49 @@ __device__ FRNTT_INLINE void run_pass_plan(u32x4* lds, i32x4* lds_f, const PassP
   using PL = PassPlan<M0, M1, M2>;
   constexpr int LT = kMaxLogT;  // staged elements 2^12
   stage_bat<M0, kMfmaThreads>(lds_f, T, P.dir);
-  if constexpr (PL::kStage1) stage_bat<M1, kMfmaThreads>(lds_f + PL::kOff1, T, P.dir);
+  if constexpr (PL::kStage1) stage_bat<(M1 > 0 ? M1 : 1), kMfmaThreads>(lds_f + PL::kOff1, T, P.dir);
   if constexpr (PL::kStage2) stage_bat<(M2 > 0 ? M2 : 1), kMfmaThreads>(lds_f + PL::kOff2, T, P.dir);
   load_lines<kMfmaThreads>(lds, P, T, wg);
   __syncthreads();
-  mfma_level<M0, (1 << (LT - M0 - 8)), 1>(lds, lds_f, P, T, level_geom(M0, 0, M1 + M2, M1), false, wg);
-  if constexpr (M2 > 0) {
-    mfma_level<M1, (1 << (LT - M1 - 8)), 1>(lds, lds_f + PL::kOff1, P, T, level_geom(M1, M0, M2, M2), false, wg);
-    plan_last_level<M2>(lds, lds_f + PL::kOff2, P, T, level_geom(M2, M0 + M1, 0, 0), wg);
+  if constexpr (M1 == 0) {
+    plan_last_level<M0>(lds, lds_f, P, T, level_geom(M0, 0, 0, 0), wg);
   } else {
-    plan_last_level<M1>(lds, lds_f + PL::kOff1, P, T, level_geom(M1, M0, 0, 0), wg);
+    mfma_level<M0, (1 << (LT - M0 - 8)), 1>(lds, lds_f, P, T, level_geom(M0, 0, M1 + M2, M1), false, wg);
+    if constexpr (M2 > 0) {
+      mfma_level<M1, (1 << (LT - M1 - 8)), 1>(lds, lds_f + PL::kOff1, P, T, level_geom(M1, M0, M2, M2), false, wg);
+      plan_last_level<M2>(lds, lds_f + PL::kOff2, P, T, level_geom(M2, M0 + M1, 0, 0), wg);
+    } else {
+      plan_last_level<M1>(lds, lds_f + PL::kOff1, P, T, level_geom(M1, M0, 0, 0), wg);
+    }
   }
   store_lines<kMfmaThreads>(lds, P, T, wg, false);
 }
 
-// ENGINE: 0 butterfly only, 1 MFMA only, 2 per-pass choice (P.engine).
-// NT: threads per workgroup (the MFMA engine runs with kMfmaThreads).
-template <int ENGINE, int NT>
-__device__ FRNTT_INLINE void run_pass(u32x4* lds, i32x4* lds_f, const PassParams& P, const DevTables& T,
-                                      int64_t wg) {
-  static_assert(ENGINE == 0 || NT == kMfmaThreads, "MFMA levels assume kMfmaThreads");
-  const bool use_mfma = ENGINE == 1 || (ENGINE == 2 && P.engine == 1);
-  if (use_mfma) stage_pass_bats<NT>(lds_f, P, T);
+// One pass on the butterfly engine with NT threads per workgroup.
+template <int NT>
+__device__ FRNTT_INLINE void run_pass_bfly(u32x4* lds, const PassParams& P, const DevTables& T, int64_t wg) {
   load_lines<NT>(lds, P, T, wg);
   __syncthreads();
-  if (use_mfma) mfma_levels(lds, lds_f, P, T, wg);
-  else bfly_stages<NT>(lds, P, T);
-  store_lines<NT>(lds, P, T, wg, !use_mfma);
+  bfly_stages<NT>(lds, P, T);
+  store_lines<NT>(lds, P, T, wg, true);
 }
+
+// Plan kernels of the matrix form, one per level split of a 4096-element
+// tile (each in a translation unit of its own, so that they compile in
+// parallel), and the dispatcher that finds the one for a split.
+// The first twelve are the default splits of a pass radix 2^12 .. 2^1 (fewest
+// levels of at most 16, larger first); the last four are the other orders of
+// the 2^10 and 2^11 splits, which the autotuner may choose.
+#define FRNTT_PLAN_KERNELS(X) \
+  X(4, 4, 4) X(4, 4, 3) X(4, 3, 3) X(3, 3, 3) X(4, 4, 0) X(4, 3, 0) X(3, 3, 0) X(3, 2, 0) \
+  X(4, 0, 0) X(3, 0, 0) X(2, 0, 0) X(1, 0, 0) X(3, 4, 3) X(3, 3, 4) X(3, 4, 4) X(4, 3, 4)
+#define FRNTT_DECLARE_PLAN_KERNEL(a, b, c) __global__ void ntt_plan_kernel_##a##b##c(PassParams P, DevTables T);
+FRNTT_PLAN_KERNELS(FRNTT_DECLARE_PLAN_KERNEL)
+#define FRNTT_DEFINE_PLAN_KERNEL(a, b, c)                                                  \
+  __global__ __launch_bounds__(kMfmaThreads) void ntt_plan_kernel_##a##b##c(PassParams P, DevTables T) { \
+    __shared__ u32x4 lds[2 << kMaxLogT];                                                 \
+    __shared__ i32x4 lds_f[PassPlan<a, b, c>::kLds];                                     \
+    run_pass_plan<a, b, c>(lds, lds_f, P, T, logical_wg(P));                             \
+  }
 
 }  // namespace frntt

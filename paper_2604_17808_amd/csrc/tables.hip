@@ -160,20 +160,27 @@ static void fill_tables(uint8_t* h, const Layout& L) {
             const int hh = lane & 31, a = 16 * (lane >> 5) + i;
             blk[(size_t)j * 1024 + lane * 16 + i] = dig[((size_t)j * 32 + a) * 32 + hh];
           }
+      // Seeds of the even/odd accumulators of output pair k' < rho/2 (the
+      // even-digit sum e and the odd-digit sum o of w^(k' n) x_n; outputs k'
+      // and k' + rho/2 are e + o and e - o): the signed-digit correction
+      // 128 * sum_(n of that parity, a) E[(k',h),(n,a)] for each row h, plus
+      // the row offsets on the even accumulator only, so that both e + o and
+      // e - o carry them once.
       int32_t* init = (int32_t*)(h + L.bat_init[d][m]);
-      for (int k = 0; k < rho; ++k) {
-        int32_t S[32] = {0};
-        for (int n = 0; n < rho; ++n) {
-          const int j = (k * n) & (rho - 1);
-          for (int a = 0; a < 32; ++a)
-            for (int hh = 0; hh < 32; ++hh) S[hh] += dig[((size_t)j * 32 + a) * 32 + hh];
-        }
-        for (int half2 = 0; half2 < 2; ++half2)
-          for (int rg = 0; rg < 16; ++rg) {
-            const int hh = 8 * (rg >> 2) + 4 * half2 + (rg & 3);
-            init[(k * 2 + half2) * 16 + rg] = 128 * S[hh] + beta[hh];
+      for (int k = 0; k < rho / 2; ++k)
+        for (int par = 0; par < 2; ++par) {
+          int32_t S[32] = {0};
+          for (int n = par; n < rho; n += 2) {
+            const int j = (k * n) & (rho - 1);
+            for (int a = 0; a < 32; ++a)
+              for (int hh = 0; hh < 32; ++hh) S[hh] += dig[((size_t)j * 32 + a) * 32 + hh];
           }
-      }
+          for (int half2 = 0; half2 < 2; ++half2)
+            for (int rg = 0; rg < 16; ++rg) {
+              const int hh = 8 * (rg >> 2) + 4 * half2 + (rg & 3);
+              init[((2 * k + par) * 2 + half2) * 16 + rg] = 128 * S[hh] + (par == 0 ? beta[hh] : 0);
+            }
+        }
     }
   }
 }

@@ -18,6 +18,7 @@ _LIB_PATH = os.path.join(HERE, "libfrntt.so")
 FWD, INV, COSET, COSET_INV = 0, 1, 2, 3
 ALGO_AUTO, ALGO_BUTTERFLY, ALGO_FOURSTEP_MFMA = 0, 1, 2
 VALIDATE = 1
+SPLIT_TWIDDLES = 2
 
 OK, EINVAL, ERANGE, EALIGN, ENOMEM, EHIP, EBUSY, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
 
@@ -45,6 +46,7 @@ SIGNATURES = {
     "frntt_get_algo": (_i, [_vp]),
     "frntt_set_plan": (_i, [_vp, _i, _i, ctypes.POINTER(_i), _i]),
     "frntt_get_plan": (_i, [_vp, _i, _i, ctypes.POINTER(_i), _i]),
+    "frntt_get_plan_levels": (_i, [_vp, _i, _i, _i, ctypes.POINTER(_i), _i]),
     "ntt_batch": (_i, [_vp, ctypes.POINTER(Job), _i, _vp]),
     "ntt_batch_graph": (_i, [_vp, ctypes.POINTER(Job), _i, _vp]),
     "frntt_tune": (_i, [_vp, _i, _i, ctypes.POINTER(_i), ctypes.POINTER(_i),
@@ -67,6 +69,7 @@ SIGNATURES = {
     "frntt_server_set_release_on_done": (_i, [_vp, _i]),
     "frntt_server_stats": (_i, [_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64),
                                 ctypes.POINTER(_u64)]),
+    "frntt_server_peak_inflight": (_i, [_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64)]),
     "frntt_server_destroy": (_i, [_vp]),
 }
 
@@ -172,6 +175,13 @@ class Context:
         arr = (_i * max(1, len(pass_logs)))(*pass_logs)
         return _check(lib().frntt_set_plan(self._h, algo, log_n, arr, len(pass_logs)), "frntt_set_plan")
 
+    def get_plan_levels(self, algo: int, log_n: int, pass_index: int):
+        arr = (_i * 3)()
+        n = lib().frntt_get_plan_levels(self._h, algo, log_n, pass_index, arr, 3)
+        if n < 0:
+            _check(n, "frntt_get_plan_levels")
+        return list(arr[:n])
+
     def get_plan(self, algo: int, log_n: int):
         arr = (_i * 4)()
         n = lib().frntt_get_plan(self._h, algo, log_n, arr, 4)
@@ -256,7 +266,11 @@ class Server:
         c, b, p = _u64(), _u64(), _u64()
         _check(lib().frntt_server_stats(self._h, ctypes.byref(c), ctypes.byref(b), ctypes.byref(p)),
                "frntt_server_stats")
-        return {"completed": c.value, "batches": b.value, "peak_bytes": p.value}
+        pb, pr = _u64(), _u64()
+        _check(lib().frntt_server_peak_inflight(self._h, ctypes.byref(pb), ctypes.byref(pr)),
+               "frntt_server_peak_inflight")
+        return {"completed": c.value, "batches": b.value, "peak_bytes": p.value,
+                "peak_inflight_batches": pb.value, "peak_inflight_requests": pr.value}
 
     def close(self):
         if getattr(self, "_h", None):
