@@ -24,13 +24,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
-INT8_PEAK_TOPS = 5000.0        # MI355X dense int8 MFMA, TOP/s
-# 32x32+64-bit integer multiply-adds: 256 CUs x 64 lanes x 2.4 GHz, one per
-# lane per clock (the lane rate of the 78.6 TFLOP/s fp64 vector peak)
-MAD_PEAK_TMADS = 256 * 64 * 2.4e9 / 1e12
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s (published)
+INT8_PEAK_TOPS = 5000.0        # MI355X dense int8 MFMA, TOP/s (published)
+# The VALU peak for the 32x32+64-bit multiply-add (v_mad_u64_u32) is not a
+# published figure: it is measured live by the saturating kernel of
+# libfrntt_peaks.so (256 workgroups, 1..4 waves per SIMD, the best rate).
 MADS_PER_PRODUCT = 162         # Montgomery product on nine 29-bit limbs (9 rows x 18)
-MADS_PER_MERGE = 20            # carry merge: 12 for the word groups + 8 for the quotient step
+MADS_PER_MERGE = 32            # carry merge: 24 for the word groups + 8 for the quotient step
 PASS_TABLE_MAX_LOG = 25        # the library keeps a twiddle table for non-last passes up to 2^25 entries
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_mfma_fwd_2e20.txt")
 KERNEL_SOURCES = ["fr.hpp", "ntt_device.hpp", "ntt_levels.hpp", "ntt_pass_mfma.hip"]
@@ -109,7 +109,9 @@ def algorithmic_work(plan, kind=0):
         # HBM: read and write every element; a non-last pass also reads its
         # twiddle table (one 32-byte entry per element) when the library keeps one
         hbm = 64 + (32 if p + 1 < len(plan) and l + rest <= PASS_TABLE_MAX_LOG else 0)
-        out.append({"levels": levs, "mads": mads, "mfma_ops": 2048 * sum(1 << m for m in levs), "hbm_bytes": hbm})
+        # int8 operations: a radix-rho level takes rho/2 MFMAs of 32x32x32 per
+        # 32 vectors and output pair (even/odd split), i.e. 1024 rho per element
+        out.append({"levels": levs, "mads": mads, "mfma_ops": 1024 * sum(1 << m for m in levs), "hbm_bytes": hbm})
     return out
 
 
@@ -140,6 +142,36 @@ def measured_traffic():
         return None
 
 
+def measure_peaks():
+    """Sustained v_mad_u64_u32 and int8 MFMA rates of this GPU (libfrntt_peaks.so):
+    the best of 1..4 waves per SIMD on one workgroup per CU."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2604_17808_amd", "libfrntt_peaks.so"))
+    lib.frntt_peaks_run.argtypes = [ctypes.c_int] * 5 + [ctypes.POINTER(ctypes.c_double)] * 2
+    out = {}
+    for kind, name, iters in ((0, "mad_tps", 4000), (1, "mfma_tops", 4000)):
+        best = 0.0
+        for w in (1, 2, 3, 4):
+            ms, work = ctypes.c_double(), ctypes.c_double()
+            rc = lib.frntt_peaks_run(0, kind, 256, w, iters, ctypes.byref(ms), ctypes.byref(work))
+            if rc != 0:
+                raise RuntimeError(f"frntt_peaks_run failed with hipError {rc}")
+            best = max(best, work.value / (ms.value * 1e-3) / 1e12)
+        out[name] = round(best, 2)
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(log_n_sample=20, budget_s=20.0):
     """The C oracle (radix-2, OpenMP) on this host's cores, on 2^20 forward
     transforms repeated for about `budget_s` seconds."""
@@ -158,7 +190,7 @@ def cpu_baseline(log_n_sample=20, budget_s=20.0):
             break
     dt = (time.perf_counter() - t0) / reps
     return {"value": round((1 << log_n_sample) / dt / 1e6, 3), "unit": "Melem/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"{reps} forward NTTs of 2^{log_n_sample} (seed 2) with the plain C radix-2 "
                       f"oracle, OpenMP over {threads} threads, {dt * 1e3:.1f} ms each"}
 
@@ -245,9 +277,32 @@ def bench_c5(ctx, fr, n_requests):
         st = srv.stats()
         res["batches"] = st["batches"]
         res["peak_gib"] = round(st["peak_bytes"] / 2**30, 2)
+        res["peak_inflight_batches"] = st["peak_inflight_batches"]
+        res["peak_inflight_requests"] = st["peak_inflight_requests"]
+        res["generation"] = c5_generation_time(ctx, reqs)
         return res
     finally:
         srv.close()
+
+
+def c5_generation_time(ctx, reqs):
+    """Device time of generating the request data alone (the server does it on
+    the device at admission, inside each request's latency): every request of
+    the stream generated back to back into one buffer, between two events."""
+    import torch
+    biggest = max(r["log_n"] for r in reqs)
+    buf = torch.empty(((1 << biggest), 4), dtype=torch.int64, device="cuda:0")
+    stream = torch.cuda.current_stream().cuda_stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i, r in enumerate(reqs):
+        ctx.generate(buf.data_ptr(), 5, i + 1, 0, 1 << r["log_n"], stream)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    del buf
+    return {"total_ms": round(ms, 2), "mean_ms_per_request": round(ms / len(reqs), 4)}
 
 
 def main():
@@ -305,6 +360,16 @@ def main():
     mf = res["mfma"]
     out["c2"] = res
 
+    # ---- C1: 2^10 forward + inverse, butterfly form, microseconds per call
+    b10 = torch.empty((1024, 4), dtype=torch.int64, device="cuda:0")
+    ctx.generate(b10.data_ptr(), 1, 0, 0, 1024, stream)
+    c1 = {}
+    for kind_name, kind in (("fwd", fr.FWD), ("inv", fr.INV)):
+        c1[kind_name + "_us"] = round(1e3 * time_transform(ctx, torch, b10.data_ptr(), 10, 1, kind,
+                                                          fr.ALGO_BUTTERFLY, 200, 5, stream), 3)
+    out["c1"] = c1
+    del b10
+
     if "c3" in extra:
         # ---- 2^24 coset NTT then coset INTT, both forms, per transform
         log(f"timing 2^24 coset round trip")
@@ -328,7 +393,11 @@ def main():
         out["c5"] = bench_c5(ctx, fr, args.serve_requests)
 
     # ---- roofline of the dominant kernel (the MFMA pass kernel) on the
-    # headline workload: algorithmic work per launch / average launch time
+    # headline workload: algorithmic work per launch / average launch time,
+    # for each unit (Big-T): int8 MFMA, VALU multiply-adds, HBM bytes. The
+    # bound is the unit with the largest fraction of its peak.
+    log("measuring the VALU multiply-add and int8 MFMA rates")
+    peaks = measure_peaks()
     work = algorithmic_work(mf["plan"])
     launches = len(mf["plan"])
     per_launch_ms = mf["ms"] / launches
@@ -336,15 +405,31 @@ def main():
     mads = n * sum(w["mads"] for w in work) / launches
     ops = n * sum(w["mfma_ops"] for w in work) / launches
     hbm = n * sum(w["hbm_bytes"] for w in work) / launches
-    achieved = mads / t / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(MAD_PEAK_TMADS, 2),
-                "unit": "Tmad/s", "frac": round(achieved / MAD_PEAK_TMADS, 4), "traffic": measured_traffic(),
+    terms = {
+        "mfma": {"achieved": ops / t / 1e12, "peak": INT8_PEAK_TOPS, "unit": "TOP/s", "work_per_launch": ops,
+                 "peak_source": "published dense int8"},
+        "alu": {"achieved": mads / t / 1e12, "peak": peaks["mad_tps"], "unit": "Tmad/s", "work_per_launch": mads,
+                "peak_source": "measured v_mad_u64_u32 rate (libfrntt_peaks)"},
+        "hbm": {"achieved": hbm / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s", "work_per_launch": hbm,
+                "peak_source": "published HBM3E"},
+    }
+    for v in terms.values():
+        v["frac"] = round(v["achieved"] / v["peak"], 4)
+        v["achieved"] = round(v["achieved"], 3)
+    bound = max(terms, key=lambda k: terms[k]["frac"])
+    roofline = {"bound": bound, "achieved": terms[bound]["achieved"], "peak": terms[bound]["peak"],
+                "unit": terms[bound]["unit"], "frac": terms[bound]["frac"], "traffic": measured_traffic(),
                 "kernel": "ntt_pass_mfma_plan_kernel", "launch_ms": round(per_launch_ms, 5),
-                "mads_per_launch": mads,
-                "hbm": {"achieved_gbs": round(hbm / t / 1e9, 1), "peak_gbs": HBM_PEAK_GBS,
-                        "frac": round(hbm / t / 1e9 / HBM_PEAK_GBS, 4), "bytes_per_launch": hbm},
-                "mfma_int8": {"achieved_tops": round(ops / t / 1e12, 1), "peak_tops": INT8_PEAK_TOPS,
-                              "frac": round(ops / t / 1e12 / INT8_PEAK_TOPS, 4), "ops_per_launch": ops}}
+                "terms": terms, "measured_peaks": peaks}
+    if "c3" in out:
+        # C3 (2^24 coset NTT, MFMA form): achieved HBM bandwidth and int8 MFMA
+        # utilisation from the algorithmic bytes and operations of the transform
+        w3 = algorithmic_work(out["c3"]["mfma"]["plan"], kind=2)
+        n24 = 1 << 24
+        t3 = out["c3"]["mfma"]["coset_ms"] * 1e-3
+        out["c3"]["mfma"]["hbm_gbs"] = round(n24 * sum(w["hbm_bytes"] for w in w3) / t3 / 1e9, 1)
+        out["c3"]["mfma"]["mfma_util"] = round(n24 * sum(w["mfma_ops"] for w in w3) / t3 / 1e12 / INT8_PEAK_TOPS, 4)
+        out["c3"]["mfma"]["valu_mad_frac"] = round(n24 * sum(w["mads"] for w in w3) / t3 / 1e12 / peaks["mad_tps"], 4)
 
     cpu = None if args.no_cpu else cpu_baseline()
 
