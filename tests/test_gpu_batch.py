@@ -93,21 +93,28 @@ def test_batch_errors(ctx):
 
 def test_c4_uneven_256_graph(ctx):
     """256 forward NTTs, sizes uniform over 2^12..2^20 (seed 4), one persistent
-    launch captured in a hipGraph. Every replay is checked on a sample of jobs
-    (inputs regenerated eagerly between replays)."""
+    launch captured in a hipGraph. The first replay is checked on every job
+    against the oracle; later replays (inputs regenerated eagerly in between)
+    and the same batch without the graph on a sample."""
     sizes = si.uneven_batch_sizes(4, 256, 12, 20)
     kinds = [0] * 256
     _say(f"c4: {sum(1 << l for l in sizes)} elements in 256 jobs")
     bufs, jobs = make_jobs(ctx, 4, sizes, kinds)
+    ctx.batch(jobs, graph=True)
+    torch.cuda.synchronize()
+    got = [host(b) for b in bufs]
+    _say("c4: first replay done, checking all 256 jobs")
+    for j, l in enumerate(sizes):
+        assert np.array_equal(got[j], expect(4, j, l, 0)), (j, l)
+    del got
     rng = np.random.default_rng(4)
     sample = sorted(set(rng.choice(256, 10, replace=False).tolist()) | {int(np.argmax(sizes)),
                                                                           int(np.argmin(sizes))})
     wants = {j: expect(4, j, sizes[j], 0) for j in sample}
-    for replay in range(3):
-        if replay:
-            for j, l in enumerate(sizes):                  # eager regeneration between replays
-                ctx.generate(bufs[j].data_ptr(), 4, j, 0, 1 << l)
-            torch.cuda.synchronize()
+    for replay in range(1, 3):
+        for j, l in enumerate(sizes):                  # eager regeneration between replays
+            ctx.generate(bufs[j].data_ptr(), 4, j, 0, 1 << l)
+        torch.cuda.synchronize()
         ctx.batch(jobs, graph=True)
         torch.cuda.synchronize()
         for j in sample:
@@ -138,9 +145,42 @@ def test_autotuner(ctx, tmp_path):
     assert doc["format"] == "frntt-tune-1"
     ent = [e for e in doc["entries"] if e["log_n"] == 16][0]
     assert sum(ent["passes"]) == 16 and ent["algo"] == algo
+    assert len(ent["levels"]) == len(ent["passes"])
     c2 = fr.Context(0, max_log_n=16)
     try:
         c2.tune_load(path)
         assert c2.get_plan(fr.ALGO_AUTO, 16) == plan
     finally:
         c2.close()
+
+
+def test_tuned_level_split_single_and_batch(ctx, tmp_path):
+    """A tuned plan with non-default level orders ([3,4,3] and [3,3,4] in the
+    two 2^10 passes of 2^20) is used by single transforms and by batches, and
+    both stay bit-exact."""
+    path = str(tmp_path / "tune20.json")
+    with open(path, "w") as fh:
+        json.dump({"format": "frntt-tune-1", "entries": [
+            {"log_n": 20, "algo": 2, "passes": [10, 10], "ms": 0.1, "levels": [[3, 4, 3], [3, 3, 4]]}]}, fh)
+    c = fr.Context(0, max_log_n=20)
+    try:
+        assert c.get_plan_levels(fr.ALGO_AUTO, 20, 0) == [4, 3, 3]         # default split
+        c.tune_load(path)
+        assert c.get_plan(fr.ALGO_AUTO, 20) == [10, 10]
+        assert c.get_plan_levels(fr.ALGO_AUTO, 20, 0) == [3, 4, 3]
+        assert c.get_plan_levels(fr.ALGO_AUTO, 20, 1) == [3, 3, 4]
+        x = si.polynomial(33, 20)
+        for kind in (fr.FWD, fr.COSET_INV):
+            _say(f"tuned levels 2^20 kind={kind}")
+            t = torch.from_numpy(x.view(np.int64).copy()).to("cuda:0")
+            c.transform_checked(t.data_ptr(), 20, 1, kind)
+            torch.cuda.synchronize()
+            assert np.array_equal(host(t), cref.transform(x, 20, kind))
+        bufs, jobs = make_jobs(c, 34, [20, 14, 20], [0, 1, 3])
+        c.batch(jobs)
+        torch.cuda.synchronize()
+        for j, (l, k) in enumerate(zip([20, 14, 20], [0, 1, 3])):
+            assert np.array_equal(host(bufs[j]), expect(34, j, l, k)), (j, l, k)
+    finally:
+        torch.cuda.synchronize()
+        c.close()
