@@ -113,6 +113,20 @@ int ntt_transform(frntt_ctx *ctx, void *data, int log_n, int batch, int kind, vo
 int ntt_transform_algo(frntt_ctx *ctx, void *data, int log_n, int batch, int kind, int algo,
                        void *stream);
 
+/* For callers that cannot allocate: code under hipGraph stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc. Same result as
+ * ntt_transform (bit-identical), but nothing is allocated, built or waited
+ * for on any call: the passes ping-pong through a static device array of
+ * FRNTT_NOALLOC_MAX_ELEMS elements (32 MiB) that the library holds on each GPU
+ * until the process ends, and every pass twiddle comes from the split tables
+ * built at context creation (no N-entry tables; slower than ntt_transform).
+ * batch << log_n must not exceed FRNTT_NOALLOC_MAX_ELEMS (ERANGE otherwise).
+ * All calls on one GPU share that array: calls that overlap on one GPU (other
+ * streams, other contexts, other threads) race and must be serialised by the
+ * caller. Errors otherwise as ntt_transform. */
+#define FRNTT_NOALLOC_MAX_ELEMS (1u << 20)
+int ntt_transform_noalloc(frntt_ctx *ctx, void *data, int log_n, int batch, int kind, void *stream);
+
 /* Choose the algorithm used by later calls (FRNTT_ALGO_*). */
 int frntt_set_algo(frntt_ctx *ctx, int algo);
 int frntt_get_algo(const frntt_ctx *ctx);

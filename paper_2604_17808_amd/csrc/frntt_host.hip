@@ -497,6 +497,7 @@ int frntt_ctx_create(frntt_ctx** out, int hip_device, int max_log_n, unsigned fl
   if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess) ctx->cu_count = prop.multiProcessorCount;
   if (ctx->cu_count <= 0) ctx->cu_count = 256;
   int rc = build_tables(ctx);
+  if (rc == FRNTT_OK && noalloc_scratch_address(&ctx->noalloc_scratch) != 0) rc = FRNTT_EHIP;
   if (rc == FRNTT_OK) {
     hipError_t e = hipMalloc((void**)&ctx->valid_flag, 256);
     if (e != hipSuccess) rc = FRNTT_ENOMEM;

@@ -86,6 +86,7 @@ struct frntt_ctx {
   std::atomic<size_t> table_bytes{0};  // all context tables, including pass-twiddle tables
   frntt::DevTables tables{};
   unsigned int* valid_flag = nullptr;  // device flag for FRNTT_VALIDATE
+  void* noalloc_scratch = nullptr;     // this device's static scratch of ntt_transform_noalloc
   // plan overrides [algo][log_n]
   frntt::Plan plan_override[3][29];
   bool has_override[3][29] = {};
@@ -123,6 +124,11 @@ int build_passes(frntt_ctx* ctx, const Plan& plan, int log_n, int batch, int kin
 // The same into a caller's array of at least 4 entries (no host allocation).
 int build_passes_into(frntt_ctx* ctx, const Plan& plan, int log_n, int batch, int kind, void* data,
                       void* scratch, PassParams* out, int* n_out, int algo, bool capturing, bool no_tables);
+// Largest batch << log_n of the allocation-free entry point (its static
+// device scratch holds 2^kNoallocMaxLog elements).
+constexpr int kNoallocMaxLog = 20;
+// Device address of this GPU's allocation-free scratch array (hipError_t).
+int noalloc_scratch_address(void** out);
 // One transform with an explicit plan (no plan lookup).
 int transform_plan(frntt_ctx* ctx, void* data, int log_n, int batch, int kind, int algo, const Plan& plan,
                    hipStream_t stream, void* workspace, size_t ws_bytes);

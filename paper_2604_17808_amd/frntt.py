@@ -42,6 +42,7 @@ SIGNATURES = {
     "ntt_coset_inv": (_i, [_vp, _vp, _i, _i, _vp]),
     "ntt_transform": (_i, [_vp, _vp, _i, _i, _i, _vp]),
     "ntt_transform_algo": (_i, [_vp, _vp, _i, _i, _i, _i, _vp]),
+    "ntt_transform_noalloc": (_i, [_vp, _vp, _i, _i, _i, _vp]),
     "frntt_set_algo": (_i, [_vp, _i]),
     "frntt_get_algo": (_i, [_vp]),
     "frntt_set_plan": (_i, [_vp, _i, _i, ctypes.POINTER(_i), _i]),
