@@ -33,7 +33,9 @@ MADS_PER_PRODUCT = 162         # Montgomery product on nine 29-bit limbs (9 rows
 MADS_PER_MERGE = 32            # carry merge: 24 for the word groups + 8 for the quotient step
 PASS_TABLE_MAX_LOG = 25        # the library keeps a twiddle table for non-last passes up to 2^25 entries
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_mfma_fwd_2e20.txt")
-KERNEL_SOURCES = ["fr.hpp", "ntt_device.hpp", "ntt_levels.hpp", "ntt_pass_mfma.hip"]
+# sources of the profiled kernel: the field arithmetic, the level engine and the
+# translation unit instantiating the <4,3,3> plan kernel of the 2^20 passes
+KERNEL_SOURCES = ["fr.hpp", "ntt_device.hpp", "ntt_levels.hpp", "ntt_plan_c.hip"]
 
 
 def log(msg):
@@ -142,9 +144,10 @@ def measured_traffic():
         return None
 
 
-def measure_peaks():
+def measure_peaks(table=None):
     """Sustained v_mad_u64_u32 and int8 MFMA rates of this GPU (libfrntt_peaks.so):
-    the best of 1..4 waves per SIMD on one workgroup per CU."""
+    the best of 1..4 waves per SIMD on one workgroup per CU. Each run's rate
+    is appended to `table` if given."""
     import ctypes
     lib = ctypes.CDLL(os.path.join(ROOT, "paper_2604_17808_amd", "libfrntt_peaks.so"))
     lib.frntt_peaks_run.argtypes = [ctypes.c_int] * 5 + [ctypes.POINTER(ctypes.c_double)] * 2
@@ -156,7 +159,11 @@ def measure_peaks():
             rc = lib.frntt_peaks_run(0, kind, 256, w, iters, ctypes.byref(ms), ctypes.byref(work))
             if rc != 0:
                 raise RuntimeError(f"frntt_peaks_run failed with hipError {rc}")
-            best = max(best, work.value / (ms.value * 1e-3) / 1e12)
+            rate = work.value / (ms.value * 1e-3) / 1e12
+            if table is not None:
+                table.append({"kernel": name, "waves_per_simd": w, "ms": round(ms.value, 4),
+                              "work": work.value, "rate_t_per_s": round(rate, 3)})
+            best = max(best, rate)
         out[name] = round(best, 2)
     return out
 
@@ -193,6 +200,41 @@ def cpu_baseline(log_n_sample=20, budget_s=20.0):
             "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"{reps} forward NTTs of 2^{log_n_sample} (seed 2) with the plain C radix-2 "
                       f"oracle, OpenMP over {threads} threads, {dt * 1e3:.1f} ms each"}
+
+
+def plan_kernel_name(ctx, algo, log_n):
+    """Name of the tile kernel the first pass of 2^log_n runs (ntt_plan_kernel_abc
+    for in-tile levels of 2^a, 2^b, 2^c)."""
+    levs = ctx.get_plan_levels(algo, log_n, 0)
+    return "ntt_plan_kernel_" + "".join(str(v) for v in (levs + [0, 0, 0])[:3])
+
+
+def bench_f1(ctx, torch, fr, stream, steps):
+    """Two HBM passes against three (the recursive five-step split) at 2^22 and
+    2^24, both forms, forward: time per transform and the pass-twiddle table
+    memory each plan adds."""
+    out = {}
+    for log_n, plans in ((22, ([11, 11], [8, 7, 7])), (24, ([12, 12], [8, 8, 8]))):
+        n = 1 << log_n
+        buf = torch.empty((n, 4), dtype=torch.int64, device="cuda:0")
+        ctx.generate(buf.data_ptr(), 6, 0, 0, n, stream)
+        row = {}
+        for name, algo in (("mfma", fr.ALGO_FOURSTEP_MFMA), ("butterfly", fr.ALGO_BUTTERFLY)):
+            for plan in plans:
+                log(f"f1: 2^{log_n} {name} plan {plan}")
+                ctx.set_plan(algo, log_n, plan)
+                before = ctx.table_bytes()
+                ctx.transform_checked(buf.data_ptr(), log_n, 1, fr.FWD, stream, algo)   # builds its tables
+                torch.cuda.synchronize()
+                table = ctx.table_bytes() - before
+                t = time_transform(ctx, torch, buf.data_ptr(), log_n, 1, fr.FWD, algo, steps, 2, stream)
+                row[f"{name}_{'x'.join(map(str, plan))}"] = {
+                    "ms": round(t, 4), "melem_s": round(n / (t * 1e-3) / 1e6, 1),
+                    "table_mib_added": round(table / 2**20, 1)}
+            ctx.set_plan(algo, log_n, [])
+        out[f"2e{log_n}"] = row
+        del buf
+    return out
 
 
 def bench_c4(ctx, torch, fr, stream, replays):
@@ -312,14 +354,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing on host cores")
     ap.add_argument("--quick", action="store_true", help="headline config only")
-    ap.add_argument("--only", default="c3,c4,c5",
-                    help="comma list of the other configurations to run (c3, c4, c5)")
+    ap.add_argument("--only", default="c3,c4,c5,f1",
+                    help="comma list of the other configurations to run (c3, c4, c5, f1)")
     ap.add_argument("--c4-replays", type=int, default=200)
     ap.add_argument("--calib", action="store_true",
                     help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--settle-s", type=float, default=1.0,
                     help="untimed seconds of alternating transforms before the first timed region")
+    ap.add_argument("--peaks", action="store_true",
+                    help="only run the multiply-add and int8 MFMA rate microbenchmarks and print their table")
     args = ap.parse_args()
     extra = set() if args.quick else {c.strip() for c in args.only.split(",") if c.strip()}
     if args.gpus != 1:
@@ -331,6 +375,11 @@ def main():
     import paper_2604_17808_amd as fr
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.peaks:
+        table = []
+        best = measure_peaks(table)
+        print(json.dumps({"peaks": best, "runs": table}), flush=True)
+        return
     ctx = fr.Context(0, max_log_n=24)
     stream = torch.cuda.current_stream().cuda_stream
     out = {}
@@ -359,6 +408,9 @@ def main():
         res[name] = {"ms": t, "melem_s": n / (t * 1e-3) / 1e6, "plan": ctx.get_plan(algo, log_n)}
     mf = res["mfma"]
     out["c2"] = res
+    # the tile kernel the timed passes ran (the autotuner of the batch may
+    # change the plan of 2^20 later)
+    headline_kernel = plan_kernel_name(ctx, fr.ALGO_FOURSTEP_MFMA, log_n)
 
     # ---- C1: 2^10 forward + inverse, butterfly form, microseconds per call
     b10 = torch.empty((1024, 4), dtype=torch.int64, device="cuda:0")
@@ -387,6 +439,8 @@ def main():
         out["c3"] = c3
         del b24
 
+    if "f1" in extra:
+        out["f1"] = bench_f1(ctx, torch, fr, stream, max(3, args.steps // 10))
     if "c4" in extra:
         out["c4"] = bench_c4(ctx, torch, fr, stream, args.c4_replays)
     if "c5" in extra:
@@ -419,7 +473,7 @@ def main():
     bound = max(terms, key=lambda k: terms[k]["frac"])
     roofline = {"bound": bound, "achieved": terms[bound]["achieved"], "peak": terms[bound]["peak"],
                 "unit": terms[bound]["unit"], "frac": terms[bound]["frac"], "traffic": measured_traffic(),
-                "kernel": "ntt_pass_mfma_plan_kernel", "launch_ms": round(per_launch_ms, 5),
+                "kernel": headline_kernel, "launch_ms": round(per_launch_ms, 5),
                 "terms": terms, "measured_peaks": peaks}
     if "c3" in out:
         # C3 (2^24 coset NTT, MFMA form): achieved HBM bandwidth and int8 MFMA
