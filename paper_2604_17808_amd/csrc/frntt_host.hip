@@ -252,6 +252,14 @@ int build_passes_into(frntt_ctx* ctx, const Plan& plan_in, int log_n, int batch,
     out[(*n_out)++] = P;
     d += l;
   }
+  // The matrix form leaves the outputs of a non-last pass below 2r, which
+  // only its own first level reads: all passes of a transform run on one
+  // engine. (With a full tile every pass has a plan kernel, so this only
+  // guards the rule.)
+  bool all_mfma = true;
+  for (int i = 0; i < *n_out; ++i) all_mfma = all_mfma && out[i].engine == 1;
+  if (!all_mfma)
+    for (int i = 0; i < *n_out; ++i) out[i].engine = 0;
   return FRNTT_OK;
 }
 

@@ -84,14 +84,13 @@ __device__ FRNTT_INLINE void load_lines(u32x4* lds, const PassParams& P, const D
   }
 }
 
-// Write output k of every line (found at LDS row k, or bitrev(k) after the
-// butterfly engine) to HBM. The butterfly engine applies here the pass
-// twiddle w^(rest * k) of the size-2^(l+S) sub-problem, or the last pass's
-// N^-1 / N^-1 g^-k epilogue; the MFMA engine has applied them in its last
-// level.
+// Butterfly engine: write output k of every line (found at LDS row
+// bitrev(k)) to HBM, applying the pass twiddle w^(rest * k) of the
+// size-2^(l+S) sub-problem, or the last pass's N^-1 / N^-1 g^-k epilogue.
+// (The MFMA engine applies them in its last level, which stores its outputs
+// itself.)
 template <int NT>
-__device__ FRNTT_INLINE void store_lines(const u32x4* lds, const PassParams& P, const DevTables& T, int64_t wg,
-                                         bool bitrev) {
+__device__ FRNTT_INLINE void store_lines(const u32x4* lds, const PassParams& P, const DevTables& T, int64_t wg) {
   const int T_el = 1 << P.log_t;
   const int G = 1 << P.log_g;
   const int tid = threadIdx.x;
@@ -99,15 +98,10 @@ __device__ FRNTT_INLINE void store_lines(const u32x4* lds, const PassParams& P, 
 #pragma unroll 2
   for (int e = tid; e < T_el; e += NT) {
     const int k = e >> P.log_g, line = e & (G - 1);
-    const int row = bitrev ? (int)(__builtin_bitreverse32((uint32_t)k) >> (32 - P.log_r)) : k;
+    const int row = (int)(__builtin_bitreverse32((uint32_t)k) >> (32 - P.log_r));
     fr_t y = lds_ld(lds, row * G + line);
     const LineMap mp = map_line(P, wg * G + line);
-    // y is below 3r after the MFMA engine (canonical after the butterfly)
-    // (the MFMA engine applies the pass twiddle or the epilogue in its last
-    // level and leaves only forward outputs below 3r)
-    if (!bitrev) {
-      if (P.is_last && P.post == 0) y = fr_reduce_3r(y);
-    } else if (!P.is_last) {
+    if (!P.is_last) {
       const fr_t tw = P.pass_tw ? ld_elem(P.pass_tw, ((int64_t)k << P.log_s) + mp.rest)
                                 : pow_tw(T, P.dir, P.log_r + P.log_s, (uint64_t)mp.rest * (uint64_t)k);
       y = mont_mul(tw, y);
@@ -345,12 +339,15 @@ constexpr int bat_lds_size() { return (1 << M) * 72; }  // i32x4 units
 //           sub-problem (one Montgomery product, output left below 2r),
 //   KIND 2: the pass twiddle w^(rest k) of the size-2^(l + S) sub-problem
 //           (last level of a non-last pass; the twiddle is the product of two
-//           table entries: two Montgomery products),
+//           table entries: two Montgomery products, output left below 2r),
 //   KIND 3: the inverse transform's N^-1 (last level of the last pass),
 //   KIND 4: the coset inverse's N^-1 g^-k (g^-k from two table entries:
 //           three Montgomery products),
 //   KIND 5: the pass twiddle read from the pass's twiddle table (one
-//           Montgomery product).
+//           Montgomery product, output left below 2r).
+// Outputs of a non-last pass stay below 2r: the next pass is on the matrix
+// form too (every pass of a transform has a full tile), and its first level
+// reads only their 32 bytes.
 template <int KIND>
 struct PairWork {
   static constexpr int kProducts = KIND == 0 ? 0 : (KIND == 2 || KIND == 6) ? 2 : KIND == 4 ? 3 : 1;
@@ -376,12 +373,15 @@ struct PairWork {
     if constexpr (S < P0) {
       mg.template step<S>();
       if constexpr (S == P0 - 1) y = mg.result();
-    } else if constexpr (KIND == 1) {
+    } else if constexpr (KIND == 1 || KIND == 5) {
       prod<S - P0, true>(tw, y, y);
-    } else if constexpr (KIND == 3 || KIND == 5 || KIND == 7) {
+    } else if constexpr (KIND == 3 || KIND == 7) {
       prod<S - P0>(tw, y, y);
-    } else if constexpr (KIND == 2 || KIND == 6) {
-      if constexpr (S < P1) prod<S - P0>(tw, tw2, tw);
+    } else if constexpr (KIND == 2) {
+      if constexpr (S < P1) prod<S - P0, true>(tw, tw2, tw);
+      else prod<S - P1, true>(tw, y, y);
+    } else if constexpr (KIND == 6) {
+      if constexpr (S < P1) prod<S - P0, true>(tw, tw2, tw);
       else prod<S - P1>(tw, y, y);
     } else {
       if constexpr (S < P1) prod<S - P0>(tw, tw2, tw);          // g^-k
@@ -455,7 +455,7 @@ struct TileLoop {
       // KIND 2, 5: the line's pass-twiddle row; KIND 4: the line's output base
       // and stride inside its polynomial
       LineMap mp{};
-      if (KIND == 2 || KIND == 4 || KIND == 5 || KIND == 6) mp = map_line(P, wg * (1 << P.log_g) + (v & ((1 << P.log_g) - 1)));
+      if (KIND != 1) mp = map_line(P, wg * (1 << P.log_g) + (v & ((1 << P.log_g) - 1)));
       const int64_t rest = mp.rest;
 #pragma unroll 1
       for (int kp = 0; kp < NKP; ++kp) {
@@ -485,7 +485,15 @@ struct TileLoop {
         } else {
           wk.template steps<0, PairWork<KIND>::kSteps>();
         }
-        lds_st(lds, level_out_pos(P, g, v, k), wk.y);
+        if constexpr (KIND == 1) {
+          lds_st(lds, level_out_pos(P, g, v, k), wk.y);
+        } else {
+          // last level: the output goes straight to HBM, while the next
+          // pairs compute (forward outputs of the last pass are below 3r)
+          fr_t y = wk.y;
+          if constexpr (KIND == 0) y = fr_reduce_3r(y);
+          st_elem(P.dst, mp.out_base + ((int64_t)(kk + (k << g.pprev_log)) << mp.out_shift), y);
+        }
       }
       TileLoop<M, TPW, KIND, T + 1>::run(lds, lds_f, init, P, Tb, g, B, tile0, col, half, lane, wg, n0, n1, wk);
     }
@@ -498,8 +506,9 @@ struct TileLoop {
 // n), so that after the barrier the level can overwrite LDS in place. The
 // output pairs of a wave form a software pipeline: while the MFMAs of pair
 // i + 1 run, pair i is merged, reduced below 3r, multiplied by its
-// inter-level or pass twiddle and written to the
-// position the next level reads (KIND: see PairWork).
+// inter-level or pass twiddle and written to the position the next level
+// reads, or, in the last level, straight to its place in HBM (KIND: see
+// PairWork).
 template <int M, int TPW, int KIND>
 __device__ FRNTT_INLINE void mfma_level(u32x4* lds, i32x4* blk, const PassParams& P, const DevTables& T,
                                         const LevelGeom& g, bool stage, int64_t wg) {
@@ -603,7 +612,7 @@ __device__ FRNTT_INLINE void run_pass_plan(u32x4* lds, i32x4* lds_f, const PassP
       plan_last_level<M1>(lds, lds_f + PL::kOff1, P, T, level_geom(M1, M0, 0, 0), wg);
     }
   }
-  store_lines<kMfmaThreads>(lds, P, T, wg, false);
+  // the last level has written the pass's outputs to HBM
 }
 
 // One pass on the butterfly engine with NT threads per workgroup.
@@ -612,7 +621,7 @@ __device__ FRNTT_INLINE void run_pass_bfly(u32x4* lds, const PassParams& P, cons
   load_lines<NT>(lds, P, T, wg);
   __syncthreads();
   bfly_stages<NT>(lds, P, T);
-  store_lines<NT>(lds, P, T, wg, true);
+  store_lines<NT>(lds, P, T, wg);
 }
 
 // Plan kernels of the matrix form, one per level split of a 4096-element
