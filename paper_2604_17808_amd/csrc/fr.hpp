@@ -126,6 +126,12 @@ struct MontMul {
     to_limbs29(a, al);
     to_limbs29(b, bl);
   }
+  // a given as its nine 29-bit limbs (a table entry kept in that form)
+  __device__ FRNTT_INLINE void load(const uint32_t* a_limbs, const fr_t& b) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) al[k] = a_limbs[k];
+    to_limbs29(b, bl);
+  }
   __device__ FRNTT_INLINE void row(int i) {
     if (i == 0) {
 #pragma unroll

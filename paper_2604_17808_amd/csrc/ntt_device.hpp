@@ -28,15 +28,16 @@ struct DevTables {
   const u32x4* tw_lo[2];      // [dir] mont w28^(+-j), j < 2^14            (w28 = w_{2^28})
   const u32x4* tw_hi[2];      // [dir] mont w28^(+-(2^14 j)), j < 2^14
   const u32x4* w4096[2];      // [dir] mont w_4096^(+-j), j < 4096
+  const u32x4* w4096_l[2];    // [dir] the same as nine 29-bit limbs (3 x 16 B per entry)
   const u32x4* g_lo[2];       // [0] mont g^j, [1] mont g^-j, j < 2^14 (g = 5)
   const u32x4* g_hi[2];       // [0] mont g^(2^14 j), [1] g^-(2^14 j)
   const u32x4* ninv;          // mont 2^-L for L = 0..28
   const i32x4* bat[2][6];     // [dir][log rho] rho blocks x 64 lanes x 16 B of signed digits
   const i32x4* bat_init[2][6];// [dir][log rho] rho x 2 halves x 16 int32 accumulator seeds
-  // 2^8, 2^16, 2^24: the byte-plane weights of the carry merge, passed as
-  // kernel arguments so that the word sums stay 32x32+64-bit multiply-adds
+  // 2^8, 2^16, 2^24 and 1: the byte-plane weights of the carry merge, passed
+  // as kernel arguments so that the word sums stay 32x32+64-bit multiply-adds
   // (which overlap with MFMA) instead of becoming 64-bit shift-adds
-  uint32_t byte_w[3];
+  uint32_t byte_w[4];
 };
 
 // One HBM pass of the multi-pass transform.
@@ -130,6 +131,16 @@ __device__ FRNTT_INLINE fr_t pow_tw(const DevTables& T, int dir, int log_m, uint
 __device__ FRNTT_INLINE fr_t small_tw(const DevTables& T, int dir, int log_r, uint32_t e) {
   uint32_t idx = (e & ((1u << log_r) - 1)) << (12 - log_r);
   return ld_elem(T.w4096[dir], idx);
+}
+
+// The same twiddle as the nine 29-bit limbs of the Montgomery product.
+__device__ FRNTT_INLINE void small_tw_limbs(const DevTables& T, int dir, int log_r, uint32_t e, uint32_t* l) {
+  const uint32_t idx = (e & ((1u << log_r) - 1)) << (12 - log_r);
+  const u32x4* p = T.w4096_l[dir] + 3 * idx;
+  const u32x4 a = p[0], b = p[1], c = p[2];
+  l[0] = a.x; l[1] = a.y; l[2] = a.z; l[3] = a.w;
+  l[4] = b.x; l[5] = b.y; l[6] = b.z; l[7] = b.w;
+  l[8] = c.x;
 }
 
 // Montgomery form of g^(+-i) (i < 2^28).

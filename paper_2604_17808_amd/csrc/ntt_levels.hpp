@@ -200,35 +200,41 @@ __device__ FRNTT_INLINE void bfly_stages(u32x4* lds, const PassParams& P, const 
 // top bits t of y never exceeds the true quotient floor(y / r).
 #define FR_INV_RTOP1 (1.0 / 811880051.0)  // r_top = 0x30644e72 = 811880050
 
-// Merge the byte-plane partials of two outputs (acc0 -> output k0 in lanes
-// 0..31, acc1 -> k1 in lanes 32..63) and reduce mod r. Lane l holds rows
-// h = 8i + 4*(l/32) + j in register 4i + j (the 32x32 MFMA accumulator
-// layout), i.e. the partials of 32-bit words 2i + l/32. The seeds lift every
-// partial into [0, 2^26) (their offsets add a multiple of r), so a word
-// group sum_j P_(4w+j) 2^(8j) is an unsigned value below 2^50: three 32x32+64
-// multiply-adds. After the swap of the two half-waves each lane holds the 8
-// word groups of its own output; one add-with-carry per word then gives
-// y = sum_h P_h 2^(8h) < 2^275 as nine words. A quotient estimate from the
-// top 51 bits, at most 2 below floor(y / r), brings y into [0, 3r).
+// Merge the byte-plane partials of an output pair and reduce mod r. The
+// pair comes as its even-digit and odd-digit accumulators e and o: output k0
+// (lanes 0..31 after the swap) has partials e + o, output k1 (lanes 32..63)
+// e - o. Lane l holds rows h = 8i + 4*(l/32) + j in register 4i + j (the
+// 32x32 MFMA accumulator layout), i.e. the partials of 32-bit words
+// 2i + l/32. A word group sum_j P_(4w+j) 2^(8j) of e and of o is a signed
+// 64-bit sum of four 32x32+64 multiply-adds; their sum and difference are the
+// groups of the two outputs. The seeds lift every partial of e + o and e - o
+// into [0, 2^26) (their offsets add a multiple of r), so those groups are
+// unsigned values below 2^50. After the swap of the two half-waves each lane
+// holds the 8 word groups of its own output; one add-with-carry per word
+// then gives y = sum_h P_h 2^(8h) < 2^275 as nine words. A quotient estimate
+// from the top 51 bits, at most 2 below floor(y / r), brings y into [0, 3r).
 //
 // The work is cut into kMergeSteps steps of a few instructions, so that it
 // can be spread over the MFMA issue slots of the next outputs.
 constexpr int kMergeSteps = 16;
 
 struct Merge {
-  i32x16 a0, a1;
-  uint32_t w8, w16, w24;  // 2^8, 2^16, 2^24 (kernel arguments)
+  i32x16 a0, a1;                // the pair's even and odd accumulators
+  uint32_t w1, w8, w16, w24;    // 1, 2^8, 2^16, 2^24 (kernel arguments)
   uint64_t g0[4], g1[4];
+  int64_t ge, go;
   uint64_t X[4], Y[4];
   uint32_t y[9];
   uint32_t c;
   int32_t q;
   uint32_t carry, br;
 
-  __device__ FRNTT_INLINE uint64_t group(const i32x16& a, int i) const {
-    uint64_t x = (uint64_t)(uint32_t)a[4 * i + 1] * w8 + (uint32_t)a[4 * i];
-    x = (uint64_t)(uint32_t)a[4 * i + 2] * w16 + x;
-    return (uint64_t)(uint32_t)a[4 * i + 3] * w24 + x;
+  // signed word group i of accumulator a
+  __device__ FRNTT_INLINE int64_t group(const i32x16& a, int i) const {
+    int64_t x = (int64_t)a[4 * i] * (int64_t)(int32_t)w1;
+    x = (int64_t)a[4 * i + 1] * (int64_t)(int32_t)w8 + x;
+    x = (int64_t)a[4 * i + 2] * (int64_t)(int32_t)w16 + x;
+    return (int64_t)a[4 * i + 3] * (int64_t)(int32_t)w24 + x;
   }
   __device__ FRNTT_INLINE void swap(int i) {
     auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)g0[i], (uint32_t)g1[i], false, false);
@@ -249,10 +255,15 @@ struct Merge {
   // step S of kMergeSteps
   template <int S>
   __device__ FRNTT_INLINE void step() {
-    if constexpr (S < 4) {
-      g0[S] = group(a0, S);
-    } else if constexpr (S < 8) {
-      g1[S - 4] = group(a1, S - 4);
+    if constexpr (S < 8) {
+      // even steps: group S/2 of e and o; odd steps: the outputs' groups
+      if constexpr ((S & 1) == 0) {
+        ge = group(a0, S >> 1);
+        go = group(a1, S >> 1);
+      } else {
+        g0[S >> 1] = (uint64_t)(ge + go);
+        g1[S >> 1] = (uint64_t)(ge - go);
+      }
     } else if constexpr (S == 8) {
       swap(0); swap(1);
     } else if constexpr (S == 9) {
@@ -355,6 +366,7 @@ struct PairWork {
   Merge mg;
   MontMul mm;
   fr_t tw, tw2, tw3;  // factors (Montgomery form), loaded when the pair starts
+  uint32_t twl[9];    // KIND 1: the inter-level twiddle as 29-bit limbs
   fr_t y;             // the output of the pair: below 3r for KIND 0, canonical otherwise
 
   // step Q of a Montgomery product a * b -> out (11 steps); a LAZY product
@@ -373,7 +385,10 @@ struct PairWork {
     if constexpr (S < P0) {
       mg.template step<S>();
       if constexpr (S == P0 - 1) y = mg.result();
-    } else if constexpr (KIND == 1 || KIND == 5) {
+    } else if constexpr (KIND == 1) {
+      if constexpr (S == P0) mm.load(twl, y);
+      else prod<S - P0, true>(tw, y, y);
+    } else if constexpr (KIND == 5) {
       prod<S - P0, true>(tw, y, y);
     } else if constexpr (KIND == 3 || KIND == 7) {
       prod<S - P0>(tw, y, y);
@@ -401,8 +416,8 @@ struct PairWork {
 
 // One pipelined output pair (k', k' + RHO/2) of a tile: the RHO MFMAs of
 // digits n = 0..RHO-1 accumulate into e (n even) and o (n odd) with the
-// blocks of k' n mod RHO, then n0 = e + o holds output k' and n1 = e - o
-// output k' + RHO/2 (w^((k' + RHO/2) n) = (-1)^n w^(k' n)). The work `wk` on
+// blocks of k' n mod RHO; e + o is output k' and e - o output k' + RHO/2
+// (w^((k' + RHO/2) n) = (-1)^n w^(k' n)), formed by the merge. The work `wk` on
 // the previous pair (if WORKING) advances through its steps, spread evenly
 // over the MFMA issue slots; the constant blocks are read from LDS one digit
 // ahead, and a scheduling barrier after each digit keeps the vector work
@@ -427,13 +442,11 @@ struct DigitLoop {
 // of their digits and, on the even one only, the row offsets.
 template <int RHO, bool WORKING, class W>
 __device__ FRNTT_INLINE void mfma_pair_work(const i32x4* lds_f, const i32x4* init, const i32x4 (&Bt)[RHO], int k0,
-                                            int lane, int half, i32x16& n0, i32x16& n1, W& wk) {
-  i32x16 e = load_init(init, 2 * k0, half);
-  i32x16 o = load_init(init, 2 * k0 + 1, half);
+                                            int lane, int half, i32x16& e, i32x16& o, W& wk) {
+  e = load_init(init, 2 * k0, half);
+  o = load_init(init, 2 * k0 + 1, half);
   const i32x4 a = lds_f[lane];  // k' * 0 = 0
   DigitLoop<RHO, WORKING, W, 0>::run(lds_f, Bt, k0, lane, e, o, wk, a);
-  n0 = e + o;
-  n1 = e - o;
 }
 
 // The output pairs of tile T of a wave (tiles unrolled at compile time, so
@@ -462,7 +475,7 @@ struct TileLoop {
         const int k = kp + half * NKP;  // this lane's output digit: pair kp holds kp and kp + RHO/2
         wk.mg.a0 = n0;
         wk.mg.a1 = n1;
-        if (KIND == 1) wk.tw = small_tw(Tb, P.dir, g.m + g.q_log, (uint32_t)(nn * k));
+        if (KIND == 1) small_tw_limbs(Tb, P.dir, g.m + g.q_log, (uint32_t)(nn * k), wk.twl);
         if (KIND == 2) {
           const uint64_t e = (uint64_t)rest * (uint64_t)(kk + (k << g.pprev_log));
           const uint32_t E = (uint32_t)((e << (kMasterLog - P.log_r - P.log_s)) & ((1u << kMasterLog) - 1));
@@ -537,6 +550,7 @@ __device__ FRNTT_INLINE void mfma_level(u32x4* lds, i32x4* blk, const PassParams
   }
   __syncthreads();
   PairWork<KIND> wk;
+  wk.mg.w1 = T.byte_w[3];
   wk.mg.w8 = T.byte_w[0];
   wk.mg.w16 = T.byte_w[1];
   wk.mg.w24 = T.byte_w[2];

@@ -4,7 +4,9 @@
 //   caption) and notes that tables growing with N run out of memory (3-step
 //   NTT, Introduction); here the pass twiddles w_M^e for any M <= 2^28 come
 //   from two 2^14-entry tables of w_{2^28} powers and one extra product;
-//   in-pass twiddles come from one 4096-entry table.
+//   in-pass twiddles come from one 4096-entry table, kept a second time as
+//   nine 29-bit limbs per entry (the operand form of the Montgomery product)
+//   for the matrix form's inter-level twiddles.
 // * byte-limb constant blocks for the matrix form (Alg. 1, Precomputation:
 //   the BAT-shifted constants I_{i,b} = ... << 8b mod Q and their byte split
 //   E[i,b,j,h]): for a radix rho, block j holds the signed base-256 digits
@@ -28,6 +30,21 @@ void put_elem(uint8_t* dst, const Fe& a) { std::memcpy(dst, a.v, 32); }
 
 uint8_t byte_of(const Fe& a, int h) { return (uint8_t)(a.v[h >> 3] >> (8 * (h & 7))); }
 
+// nine 29-bit limbs of a canonical value (limb k = bits [29k, 29k + 29)),
+// then three zero words: 48 bytes
+void put_limbs29(uint8_t* dst, const Fe& a) {
+  uint32_t l[12] = {};
+  for (int k = 0; k < 9; ++k) {
+    uint32_t v = 0;
+    for (int b = 0; b < 29; ++b) {
+      const int bit = 29 * k + b;
+      if (bit < 256 && ((a.v[bit >> 6] >> (bit & 63)) & 1)) v |= 1u << b;
+    }
+    l[k] = v;
+  }
+  std::memcpy(dst, l, 48);
+}
+
 // Signed base-256 digits of a canonical value: sum_h e_h 256^h = a, e_h in [-128, 127].
 void signed_digits(const Fe& a, int8_t e[32]) {
   int carry = 0;
@@ -45,7 +62,7 @@ void signed_digits(const Fe& a, int8_t e[32]) {
 }
 
 struct Layout {
-  size_t tw_lo[2], tw_hi[2], w4096[2], g_lo[2], g_hi[2], ninv;
+  size_t tw_lo[2], tw_hi[2], w4096[2], w4096_l[2], g_lo[2], g_hi[2], ninv;
   size_t bat[2][6], bat_init[2][6];
   size_t total;
 };
@@ -62,6 +79,7 @@ Layout make_layout() {
     L.tw_lo[d] = take((size_t)32 << kSplit);
     L.tw_hi[d] = take((size_t)32 << kSplit);
     L.w4096[d] = take(32 * 4096);
+    L.w4096_l[d] = take(48 * 4096);
     L.g_lo[d] = take((size_t)32 << kSplit);
     L.g_hi[d] = take((size_t)32 << kSplit);
   }
@@ -104,6 +122,7 @@ static void fill_tables(uint8_t* h, const Layout& L) {
     p = one;
     for (int j = 0; j < 4096; ++j) {
       put_elem(h + L.w4096[d] + 32 * (size_t)j, dev_m(p));
+      put_limbs29(h + L.w4096_l[d] + 48 * (size_t)j, dev_m(p));
       p = F.mul(p, w4096);
     }
     // g^(+-j) and g^(+-(2^14 j))
@@ -208,6 +227,7 @@ int build_tables(frntt_ctx* ctx) {
     T.tw_lo[d] = (const u32x4*)(b + L.tw_lo[d]);
     T.tw_hi[d] = (const u32x4*)(b + L.tw_hi[d]);
     T.w4096[d] = (const u32x4*)(b + L.w4096[d]);
+    T.w4096_l[d] = (const u32x4*)(b + L.w4096_l[d]);
     T.g_lo[d] = (const u32x4*)(b + L.g_lo[d]);
     T.g_hi[d] = (const u32x4*)(b + L.g_hi[d]);
     T.bat[d][0] = nullptr;
@@ -221,6 +241,7 @@ int build_tables(frntt_ctx* ctx) {
   T.byte_w[0] = 1u << 8;
   T.byte_w[1] = 1u << 16;
   T.byte_w[2] = 1u << 24;
+  T.byte_w[3] = 1u;
   return FRNTT_OK;
 }
 
