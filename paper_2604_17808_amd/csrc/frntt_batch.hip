@@ -5,9 +5,14 @@
 // Size): many independent polynomials share one launch so that small sizes
 // still fill the machine. Here every job is planned on its own (its pass
 // split and engine come from the context, tuned or default), all passes of
-// all jobs go into one table, and a persistent grid of resident workgroups
-// pulls (pass, workgroup) items in pass order from a device queue. A pass
-// waits for the previous pass of the same job through a per-pass counter.
+// all jobs go into one table, and persistent grids of resident workgroups
+// pull (pass, workgroup) items from a device queue: one launch per stage (the
+// first passes of all jobs, then the second passes, ...), all captured in one
+// hipGraph by ntt_batch_graph. The launch boundary orders a job's passes.
+// (A single launch whose items wait on per-pass counters needs an
+// agent-scope release and acquire around every item; those fences write
+// back and invalidate the L2 of the workgroup's XCD each time, and cost more
+// than the stages' launch boundaries.)
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -24,36 +29,31 @@ namespace {
 
 struct BatchBuild {
   std::vector<PassParams> passes;
-  std::vector<int> pass_job;
-  std::vector<int> pass_dep;
   std::vector<int64_t> pass_wgs;
   std::vector<int64_t> item_pass;
   std::vector<int64_t> item_wg;
+  std::vector<int64_t> stage_begin;  // first item of each stage, then the item count
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct DevLayout {
-  size_t passes, pass_job, pass_dep, pass_wgs, item_pass, item_wg, counters, total;
+  size_t tables, passes, item_pass, item_wg, counters, total;
 };
 
-DevLayout layout_for(size_t np, size_t ni) {
+DevLayout layout_for(size_t np, size_t ni, size_t n_stages) {
   DevLayout L;
   size_t off = 0;
+  L.tables = off;
+  off = align256(off + sizeof(DevTables));
   L.passes = off;
   off = align256(off + np * sizeof(PassParams));
-  L.pass_job = off;
-  off = align256(off + np * sizeof(int));
-  L.pass_dep = off;
-  off = align256(off + np * sizeof(int));
-  L.pass_wgs = off;
-  off = align256(off + np * sizeof(int64_t));
   L.item_pass = off;
   off = align256(off + ni * sizeof(int64_t));
   L.item_wg = off;
   off = align256(off + ni * sizeof(int64_t));
-  L.counters = off;  // [0] queue head, [1..np] done counters
-  off = align256(off + (np + 1) * sizeof(unsigned int));
+  L.counters = off;  // queue head of each stage
+  off = align256(off + n_stages * sizeof(unsigned int));
   L.total = off;
   return L;
 }
@@ -99,16 +99,12 @@ int build_batch(frntt_ctx* ctx, const frntt_job* jobs, int n_jobs, const std::ve
     if (plan.n_pass > 1 && !scratch[(size_t)j]) return FRNTT_EINVAL;
     int rc = build_passes(ctx, plan, jb.log_n, 1, jb.kind, jb.data, scratch[(size_t)j], &pp, algo, capturing);
     if (rc) return rc;
-    int prev = -1;
     for (PassParams& P : pp) {
       P.xcd_remap = 0;  // the queue decides placement
       const int idx = (int)B->passes.size();
       B->passes.push_back(P);
-      B->pass_job.push_back(j);
-      B->pass_dep.push_back(prev);
       B->pass_wgs.push_back(P.wg_count);
       job_passes[(size_t)j].push_back(idx);
-      prev = idx;
     }
     max_pass = std::max(max_pass, (int)pp.size());
   }
@@ -117,7 +113,8 @@ int build_batch(frntt_ctx* ctx, const frntt_job* jobs, int n_jobs, const std::ve
   std::vector<int> order((size_t)n_jobs);
   for (int j = 0; j < n_jobs; ++j) order[(size_t)j] = j;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return jobs[a].log_n > jobs[b].log_n; });
-  for (int s = 0; s < max_pass; ++s)
+  for (int s = 0; s < max_pass; ++s) {
+    B->stage_begin.push_back((int64_t)B->item_pass.size());
     for (int j : order) {
       if ((int)job_passes[(size_t)j].size() <= s) continue;
       const int p = job_passes[(size_t)j][(size_t)s];
@@ -126,46 +123,55 @@ int build_batch(frntt_ctx* ctx, const frntt_job* jobs, int n_jobs, const std::ve
         B->item_wg.push_back(w);
       }
     }
+  }
+  B->stage_begin.push_back((int64_t)B->item_pass.size());
   return FRNTT_OK;
 }
 
-void fill_host(uint8_t* h, const DevLayout& L, const BatchBuild& B) {
+void fill_host(uint8_t* h, const DevLayout& L, const BatchBuild& B, const DevTables& T) {
   const size_t np = B.passes.size(), ni = B.item_pass.size();
+  std::memcpy(h + L.tables, &T, sizeof(DevTables));
   std::memcpy(h + L.passes, B.passes.data(), np * sizeof(PassParams));
-  std::memcpy(h + L.pass_job, B.pass_job.data(), np * sizeof(int));
-  std::memcpy(h + L.pass_dep, B.pass_dep.data(), np * sizeof(int));
-  std::memcpy(h + L.pass_wgs, B.pass_wgs.data(), np * sizeof(int64_t));
   std::memcpy(h + L.item_pass, B.item_pass.data(), ni * sizeof(int64_t));
   std::memcpy(h + L.item_wg, B.item_wg.data(), ni * sizeof(int64_t));
-  std::memset(h + L.counters, 0, (np + 1) * sizeof(unsigned int));
+  std::memset(h + L.counters, 0, (B.stage_begin.size() - 1) * sizeof(unsigned int));
 }
 
 BatchParams params_for(uint8_t* d, const DevLayout& L, const BatchBuild& B) {
   BatchParams P;
+  P.tables = (const DevTables*)(d + L.tables);
   P.passes = (const PassParams*)(d + L.passes);
-  P.pass_job = (const int*)(d + L.pass_job);
-  P.pass_dep = (const int*)(d + L.pass_dep);
-  P.pass_wgs = (const int64_t*)(d + L.pass_wgs);
   P.item_pass = (const int64_t*)(d + L.item_pass);
   P.item_wg = (const int64_t*)(d + L.item_wg);
-  P.n_items = (int64_t)B.item_pass.size();
+  P.item_begin = 0;
+  P.item_end = 0;
   P.queue = (unsigned int*)(d + L.counters);
-  P.done = (unsigned int*)(d + L.counters) + 1;
   return P;
 }
 
-// Zero the counters and launch the persistent grid (both graph-capturable:
-// kernels only).
-int launch_batch(frntt_ctx* ctx, const BatchParams& P, size_t np, hipStream_t stream) {
-  const int64_t words = (int64_t)np + 1;
-  hipLaunchKernelGGL(zero_words_kernel, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, stream, P.queue,
-                     words);
+// Zero the stage counters, then launch one persistent grid per stage (all
+// graph-capturable: kernels only).
+int launch_batch(frntt_ctx* ctx, const BatchParams& P0, const std::vector<int64_t>& stage_begin,
+                 hipStream_t stream) {
+  const int64_t n_stages = (int64_t)stage_begin.size() - 1;
+  if (n_stages <= 0) return FRNTT_OK;
+  hipLaunchKernelGGL(zero_words_kernel, dim3((unsigned)((n_stages + 255) / 256)), dim3(256), 0, stream, P0.queue,
+                     n_stages);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_hip_error(ctx, e);
-  // one resident workgroup per CU (LDS bound); never more than there are items
-  const int64_t grid = std::min<int64_t>(P.n_items, (int64_t)ctx->cu_count);
-  hipLaunchKernelGGL(ntt_batch_kernel, dim3((unsigned)grid), dim3(kMfmaThreads), 0, stream, P, ctx->tables);
-  return set_hip_error(ctx, hipGetLastError());
+  for (int64_t s = 0; s < n_stages; ++s) {
+    BatchParams P = P0;
+    P.item_begin = stage_begin[(size_t)s];
+    P.item_end = stage_begin[(size_t)s + 1];
+    P.queue = P0.queue + s;
+    // one resident workgroup per CU (LDS bound); never more than there are items
+    const int64_t grid = std::min<int64_t>(P.item_end - P.item_begin, (int64_t)ctx->cu_count);
+    if (grid <= 0) continue;
+    hipLaunchKernelGGL(ntt_batch_kernel, dim3((unsigned)grid), dim3(kMfmaThreads), 0, stream, P);
+    e = hipGetLastError();
+    if (e != hipSuccess) return set_hip_error(ctx, e);
+  }
+  return FRNTT_OK;
 }
 
 bool same_jobs(const std::vector<frntt_job>& a, const frntt_job* b, int n) {
@@ -223,7 +229,7 @@ static int batch_launch_common(frntt_ctx* ctx, const frntt_job* jobs, int n_jobs
   rc = build_batch(ctx, jobs, n_jobs, scratch, plans, &B, false);
   if (rc) return rc;
   if (B.item_pass.empty()) return FRNTT_OK;
-  const DevLayout L = layout_for(B.passes.size(), B.item_pass.size());
+  const DevLayout L = layout_for(B.passes.size(), B.item_pass.size(), B.stage_begin.size() - 1);
   std::lock_guard<std::mutex> lk(ctx->mu);
   BatchBuffers& bb = ctx->batch_bufs[stream];
   // the previous batch on this stream may still read the buffers: wait for
@@ -253,13 +259,13 @@ static int batch_launch_common(frntt_ctx* ctx, const frntt_job* jobs, int n_jobs
     if (hipMalloc(&bb.dev, L.total) != hipSuccess) return FRNTT_ENOMEM;
     bb.dev_bytes = L.total;
   }
-  fill_host((uint8_t*)bb.host, L, B);
+  fill_host((uint8_t*)bb.host, L, B, ctx->tables);
   hipError_t e = hipMemcpyAsync(bb.dev, bb.host, L.total, hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return set_hip_error(ctx, e);
   e = hipEventRecord(bb.event, stream);
   if (e != hipSuccess) return set_hip_error(ctx, e);
   const BatchParams P = params_for((uint8_t*)bb.dev, L, B);
-  return launch_batch(ctx, P, B.passes.size(), stream);
+  return launch_batch(ctx, P, B.stage_begin, stream);
 }
 
 int batch_graph_impl(frntt_ctx* ctx, const frntt_job* jobs, int n_jobs, hipStream_t stream) {
@@ -291,13 +297,13 @@ int batch_graph_impl(frntt_ctx* ctx, const frntt_job* jobs, int n_jobs, hipStrea
   std::vector<void*> scratch((size_t)n_jobs, nullptr);
   for (int j = 0; j < n_jobs; ++j) scratch[(size_t)j] = g.scratch ? (uint8_t*)g.scratch + soff[(size_t)j] : nullptr;
   rc = build_batch(ctx, jobs, n_jobs, scratch, plans, &B, false);
-  if (rc) {
+  if (rc || B.item_pass.empty()) {  // nothing to run: every job has log_n 0
     if (g.scratch) hipFree(g.scratch);
     return rc;
   }
-  const DevLayout L = layout_for(B.passes.size(), B.item_pass.size());
+  const DevLayout L = layout_for(B.passes.size(), B.item_pass.size(), B.stage_begin.size() - 1);
   std::vector<uint8_t> host(L.total);
-  fill_host(host.data(), L, B);
+  fill_host(host.data(), L, B, ctx->tables);
   e = hipMalloc(&g.dev_buf, L.total);
   if (e != hipSuccess) {
     if (g.scratch) hipFree(g.scratch);
@@ -309,7 +315,7 @@ int batch_graph_impl(frntt_ctx* ctx, const frntt_job* jobs, int n_jobs, hipStrea
   if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
     const BatchParams P = params_for((uint8_t*)g.dev_buf, L, B);
-    rc = launch_batch(ctx, P, B.passes.size(), cap);
+    rc = launch_batch(ctx, P, B.stage_begin, cap);
     hipError_t e2 = hipStreamEndCapture(cap, &g.graph);
     if (rc == FRNTT_OK && e2 != hipSuccess) e = e2;
     if (rc != FRNTT_OK && e == hipSuccess) e = hipErrorUnknown;

@@ -15,7 +15,7 @@ namespace frntt {
 
 __global__ void ntt_pass_bfly_kernel(PassParams P, DevTables T);
 
-__global__ void ntt_batch_kernel(BatchParams B, DevTables T);
+__global__ void ntt_batch_kernel(BatchParams B);
 __global__ void generate_kernel(u32x4* out, uint64_t seed, uint64_t stream_id, uint64_t start,
                                 uint64_t count);
 __global__ void validate_kernel(const u32x4* data, uint64_t count, unsigned int* flag);

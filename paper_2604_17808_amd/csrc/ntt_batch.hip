@@ -1,6 +1,7 @@
 // Persistent kernel for uneven batches: resident workgroups pull (pass,
-// workgroup) items from a device queue; a pass waits for the previous pass
-// of its job.
+// workgroup) items of one stage (the s-th pass of every job) from a device
+// queue. The stages of a batch are consecutive launches, so a pass finds the
+// previous pass of its job complete without any wait or fence.
 #include "ntt_levels.hpp"
 
 namespace frntt {
@@ -13,17 +14,34 @@ namespace frntt {
 FRNTT_PLAN_KERNELS(FRNTT_BATCH_LDS_OK)
 #undef FRNTT_BATCH_LDS_OK
 
+// The pass descriptors and tables of a batch sit in global memory and are
+// read-only during the launch: the pass bodies read them through the
+// constant address space, at a wave-uniform address, so the reads become
+// scalar loads that no store can invalidate (through a plain reference they
+// would be reloaded from memory after every store, inside the pair loops).
+template <class S>
+__device__ FRNTT_INLINE const S& constant_ref(const S& g) {
+  const uint64_t a = (uint64_t)(uintptr_t)&g;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  const __attribute__((address_space(4))) S* c =
+      (const __attribute__((address_space(4))) S*)(((uint64_t)hi << 32) | lo);
+  return *(const S*)c;
+}
+
 // Each plan body is a function of its own (not inlined into the persistent
-// loop), so that its registers are allocated for it alone.
+// loop), so that its registers are allocated for it alone. P and T must be
+// references into global memory (the batch buffer): they are re-read through
+// the constant address space.
 template <int M0, int M1, int M2>
 __device__ __attribute__((noinline)) void batch_plan_pass(u32x4* lds, i32x4* lds_f, const PassParams& P,
                                                           const DevTables& T, int64_t wg) {
-  run_pass_plan<M0, M1, M2>(lds, lds_f, P, T, wg);
+  run_pass_plan<M0, M1, M2>(lds, lds_f, constant_ref(P), constant_ref(T), wg);
 }
 
 __device__ __attribute__((noinline)) void batch_bfly_pass(u32x4* lds, const PassParams& P, const DevTables& T,
                                                           int64_t wg) {
-  run_pass_bfly<kMfmaThreads>(lds, P, T, wg);
+  run_pass_bfly<kMfmaThreads>(lds, constant_ref(P), constant_ref(T), wg);
 }
 
 __device__ FRNTT_INLINE void run_batch_pass(u32x4* lds, i32x4* lds_f, const PassParams& P, const DevTables& T,
@@ -41,52 +59,31 @@ __device__ FRNTT_INLINE void run_batch_pass(u32x4* lds, i32x4* lds_f, const Pass
   }
 }
 
-__global__ __launch_bounds__(kMfmaThreads) void ntt_batch_kernel(BatchParams B, DevTables T) {
+__global__ __launch_bounds__(kMfmaThreads) void ntt_batch_kernel(BatchParams B) {
   __shared__ u32x4 lds[2 << kMaxLogT];
   __shared__ i32x4 lds_f[kPlanBatLds];
   // the item slot shares the constant-block area: it is written and read
   // only between passes, when no MFMA level uses that area
   int& item_sh = *reinterpret_cast<int*>(&lds_f[0]);
-  // The loop skeleton has no lane-divergent branches: the queue and counter
-  // atomics are issued by all 64 lanes of wave 0 (lane 0 adds 1, the others
-  // 0) and every loop condition is made wave-uniform with readfirstlane.
-  // A thread-0-only block at the end of a loop that contains barriers lets
-  // the compiler restructure the loop around lane 0, and the barriers then
-  // no longer pair up.
+  // The loop skeleton has no lane-divergent branches: the queue atomic is
+  // issued by all 64 lanes of wave 0 (lane 0 adds 1, the others 0) and every
+  // loop condition is made wave-uniform with readfirstlane. A thread-0-only
+  // block at the end of a loop that contains barriers lets the compiler
+  // restructure the loop around lane 0, and the barriers then no longer pair
+  // up.
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const unsigned int one = (threadIdx.x & 63) == 0 ? 1u : 0u;
   for (;;) {
     if (wave == 0) item_sh = (int)__builtin_amdgcn_readfirstlane(atomicAdd(B.queue, one));
     __syncthreads();
-    const int64_t item = __builtin_amdgcn_readfirstlane(item_sh);
+    const int64_t item = B.item_begin + __builtin_amdgcn_readfirstlane(item_sh);
     __syncthreads();
-    if (item >= B.n_items) break;
+    if (item >= B.item_end) break;
     const int p = __builtin_amdgcn_readfirstlane((int)B.item_pass[item]);
-    const int dep = __builtin_amdgcn_readfirstlane(B.pass_dep[p]);
-    if (dep >= 0) {
-      // items are handed out pass by pass, so every workgroup of `dep` was
-      // taken by a running workgroup before this one: the wait always ends
-      if (wave == 0) {
-        const unsigned int need = (unsigned int)__builtin_amdgcn_readfirstlane((int)B.pass_wgs[dep]);
-        for (;;) {
-          const unsigned int d = (unsigned int)__builtin_amdgcn_readfirstlane(
-              (int)__hip_atomic_load(&B.done[dep], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
-          if (d >= need) break;
-          __builtin_amdgcn_s_sleep(2);
-        }
-      }
-      __syncthreads();
-    }
-    // every thread reads the pass descriptor straight from global memory
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    const PassParams& P = B.passes[p];
+    const PassParams& P = B.passes[p];  // global memory
     const int64_t wg = B.item_wg[item];
-    run_batch_pass(lds, lds_f, P, T, wg);
-    __syncthreads();
-    if (wave == 0) {
-      __threadfence();
-      __hip_atomic_fetch_add(&B.done[p], one, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    run_batch_pass(lds, lds_f, P, *B.tables, wg);
+    __syncthreads();  // the next fetch rewrites the item slot
   }
 }
 

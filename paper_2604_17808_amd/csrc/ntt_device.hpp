@@ -73,14 +73,12 @@ struct PassParams {
 // Descriptor tables of one persistent batch launch (see ntt_batch_kernel).
 struct BatchParams {
   const PassParams* passes;   // all passes of all jobs
-  const int* pass_job;        // job of each pass
-  const int* pass_dep;        // index of the pass this one waits for (-1: none)
-  const int64_t* item_pass;   // pass of each work item, items ordered pass by pass
+  const int64_t* item_pass;   // pass of each work item, items ordered stage by stage
   const int64_t* item_wg;     // workgroup index of each item inside its pass
-  int64_t n_items;
-  unsigned int* queue;        // [0]: next item (zeroed before launch)
-  unsigned int* done;         // per pass: finished workgroups (zeroed before launch)
-  const int64_t* pass_wgs;    // workgroup count of each pass
+  int64_t item_begin;         // this launch's items: [item_begin, item_end)
+  int64_t item_end;
+  unsigned int* queue;        // this launch's next item (zeroed before the launches)
+  const DevTables* tables;    // the context's tables (a copy in the batch buffer)
 };
 
 // Specialised MFMA pass kernel for a 4096-element tile with these levels, or
