@@ -212,7 +212,8 @@ def plan_kernel_name(ctx, algo, log_n):
 def bench_f1(ctx, torch, fr, stream, steps):
     """Two HBM passes against three (the recursive five-step split) at 2^22 and
     2^24, both forms, forward: time per transform and the pass-twiddle table
-    memory each plan adds."""
+    memory each plan adds; and the two-pass plan with the split tables only
+    (no pass table)."""
     out = {}
     for log_n, plans in ((22, ([11, 11], [8, 7, 7])), (24, ([12, 12], [8, 8, 8]))):
         n = 1 << log_n
@@ -232,6 +233,19 @@ def bench_f1(ctx, torch, fr, stream, steps):
                     "ms": round(t, 4), "melem_s": round(n / (t * 1e-3) / 1e6, 1),
                     "table_mib_added": round(table / 2**20, 1)}
             ctx.set_plan(algo, log_n, [])
+        # the same two-pass plan with the split tables instead of a pass table
+        # (FRNTT_SPLIT_TWIDDLES: every pass twiddle is one more product)
+        sctx = fr.Context(0, max_log_n=log_n, flags=fr.frntt.SPLIT_TWIDDLES)
+        for name, algo in (("mfma", fr.ALGO_FOURSTEP_MFMA), ("butterfly", fr.ALGO_BUTTERFLY)):
+            plan = plans[0]
+            log(f"f1: 2^{log_n} {name} plan {plan}, split tables")
+            sctx.set_plan(algo, log_n, plan)
+            t = time_transform(sctx, torch, buf.data_ptr(), log_n, 1, fr.FWD, algo, steps, 2, stream)
+            row[f"{name}_{'x'.join(map(str, plan))}_split_tables"] = {
+                "ms": round(t, 4), "melem_s": round(n / (t * 1e-3) / 1e6, 1),
+                "table_mib_total": round(sctx.table_bytes() / 2**20, 2)}
+        torch.cuda.synchronize()
+        sctx.close()
         out[f"2e{log_n}"] = row
         del buf
     return out
