@@ -156,7 +156,8 @@ typedef struct {
 } frntt_job;
 
 /* Uneven batch (paper: Ablation Study - Batch Size): transform every job in
- * place with ONE persistent kernel launch. The descriptors are copied before
+ * place with persistent kernel launches, one per pass stage (the first passes
+ * of all jobs, then the second passes, ...). The descriptors are copied before
  * the call returns; the data buffers must stay alive until the stream passes
  * the call. Jobs must not overlap in memory. Errors as for ntt_transform,
  * per job, plus EINVAL for n_jobs < 0 or jobs == NULL with n_jobs > 0, and
@@ -165,8 +166,10 @@ typedef struct {
 int ntt_batch(frntt_ctx *ctx, const frntt_job *jobs, int n_jobs, void *stream);
 
 /* Graph form of ntt_batch for repeated identical batches: the first call for
- * a given job list captures the launch into a hipGraph; later calls with the
- * same list replay it. Results are identical to ntt_batch. */
+ * a given job list captures the launches into a hipGraph; later calls with the
+ * same list, whose jobs still resolve to the same form and plan (see
+ * frntt_set_algo, frntt_set_plan, frntt_tune), replay it. Results are
+ * identical to ntt_batch. */
 int ntt_batch_graph(frntt_ctx *ctx, const frntt_job *jobs, int n_jobs, void *stream);
 
 /* Autotuner: time forward transforms of one size and batch on `stream` for
@@ -254,8 +257,8 @@ int frntt_server_set_release_on_done(frntt_server *srv, int on);
 /* Counters: requests completed, batches launched, peak bytes in flight. */
 int frntt_server_stats(frntt_server *srv, uint64_t *completed, uint64_t *batches,
                        uint64_t *peak_bytes);
-/* Largest number of batches (each one persistent launch on its own slot
- * stream) and of requests that were launched and not yet complete at the
+/* Largest number of batches (each one ntt_batch launch sequence on its own
+ * slot stream) and of requests that were launched and not yet complete at the
  * same time: batches > 1 means launches were in flight together. */
 int frntt_server_peak_inflight(frntt_server *srv, uint64_t *batches, uint64_t *requests);
 /* Cancel requests not yet admitted, wait for running batches, stop the

@@ -32,13 +32,14 @@ struct BatchBuild {
   std::vector<int64_t> pass_wgs;
   std::vector<int64_t> item_pass;
   std::vector<int64_t> item_wg;
+  std::vector<int> item_cnt;
   std::vector<int64_t> stage_begin;  // first item of each stage, then the item count
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct DevLayout {
-  size_t tables, passes, item_pass, item_wg, counters, total;
+  size_t tables, passes, item_pass, item_wg, item_cnt, counters, total;
 };
 
 DevLayout layout_for(size_t np, size_t ni, size_t n_stages) {
@@ -52,6 +53,8 @@ DevLayout layout_for(size_t np, size_t ni, size_t n_stages) {
   off = align256(off + ni * sizeof(int64_t));
   L.item_wg = off;
   off = align256(off + ni * sizeof(int64_t));
+  L.item_cnt = off;
+  off = align256(off + ni * sizeof(int));
   L.counters = off;  // queue head of each stage
   off = align256(off + n_stages * sizeof(unsigned int));
   L.total = off;
@@ -86,6 +89,9 @@ int check_jobs(frntt_ctx* ctx, const frntt_job* jobs, int n_jobs, std::vector<si
   return FRNTT_OK;
 }
 
+// Tiles (workgroups of one pass) per work item.
+constexpr int64_t kTilesPerItem = 4;
+
 int build_batch(frntt_ctx* ctx, const frntt_job* jobs, int n_jobs, const std::vector<void*>& scratch,
                 const std::vector<JobPlan>& plans, BatchBuild* B, bool capturing) {
   std::vector<std::vector<int>> job_passes((size_t)n_jobs);
@@ -118,9 +124,14 @@ int build_batch(frntt_ctx* ctx, const frntt_job* jobs, int n_jobs, const std::ve
     for (int j : order) {
       if ((int)job_passes[(size_t)j].size() <= s) continue;
       const int p = job_passes[(size_t)j][(size_t)s];
-      for (int64_t w = 0; w < B->pass_wgs[(size_t)p]; ++w) {
+      // items of up to kTilesPerItem consecutive tiles: a workgroup runs
+      // them in one call (one set of register saves, one staging of the
+      // constant blocks)
+      const int64_t wgs = B->pass_wgs[(size_t)p];
+      for (int64_t w = 0; w < wgs; w += kTilesPerItem) {
         B->item_pass.push_back(p);
         B->item_wg.push_back(w);
+        B->item_cnt.push_back((int)std::min<int64_t>(kTilesPerItem, wgs - w));
       }
     }
   }
@@ -134,6 +145,7 @@ void fill_host(uint8_t* h, const DevLayout& L, const BatchBuild& B, const DevTab
   std::memcpy(h + L.passes, B.passes.data(), np * sizeof(PassParams));
   std::memcpy(h + L.item_pass, B.item_pass.data(), ni * sizeof(int64_t));
   std::memcpy(h + L.item_wg, B.item_wg.data(), ni * sizeof(int64_t));
+  std::memcpy(h + L.item_cnt, B.item_cnt.data(), ni * sizeof(int));
   std::memset(h + L.counters, 0, (B.stage_begin.size() - 1) * sizeof(unsigned int));
 }
 
@@ -143,6 +155,7 @@ BatchParams params_for(uint8_t* d, const DevLayout& L, const BatchBuild& B) {
   P.passes = (const PassParams*)(d + L.passes);
   P.item_pass = (const int64_t*)(d + L.item_pass);
   P.item_wg = (const int64_t*)(d + L.item_wg);
+  P.item_cnt = (const int*)(d + L.item_cnt);
   P.item_begin = 0;
   P.item_end = 0;
   P.queue = (unsigned int*)(d + L.counters);
@@ -174,10 +187,25 @@ int launch_batch(frntt_ctx* ctx, const BatchParams& P0, const std::vector<int64_
   return FRNTT_OK;
 }
 
-bool same_jobs(const std::vector<frntt_job>& a, const frntt_job* b, int n) {
-  if ((int)a.size() != n) return false;
+bool same_plan(const JobPlan& a, const JobPlan& b) {
+  if (a.algo != b.algo || a.plan.n_pass != b.plan.n_pass || a.plan.log_t != b.plan.log_t) return false;
+  for (int p = 0; p < 4; ++p) {
+    if (a.plan.pass_log[p] != b.plan.pass_log[p] || a.plan.nlev[p] != b.plan.nlev[p] ||
+        a.plan.lev_set[p] != b.plan.lev_set[p])
+      return false;
+    for (int l = 0; l < kMaxLevels; ++l)
+      if (a.plan.lev_log[p][l] != b.plan.lev_log[p][l]) return false;
+  }
+  return true;
+}
+
+// The captured graph of an entry serves a call with the same job list whose
+// jobs still resolve to the same form and plan.
+bool same_jobs(const GraphEntry& g, const frntt_job* b, const std::vector<JobPlan>& plans, int n) {
+  if ((int)g.jobs.size() != n) return false;
   for (int i = 0; i < n; ++i)
-    if (a[(size_t)i].data != b[i].data || a[(size_t)i].log_n != b[i].log_n || a[(size_t)i].kind != b[i].kind)
+    if (g.jobs[(size_t)i].data != b[i].data || g.jobs[(size_t)i].log_n != b[i].log_n ||
+        g.jobs[(size_t)i].kind != b[i].kind || !same_plan(g.plans[(size_t)i], plans[(size_t)i]))
       return false;
   return true;
 }
@@ -278,7 +306,7 @@ int batch_graph_impl(frntt_ctx* ctx, const frntt_job* jobs, int n_jobs, hipStrea
   {
     std::lock_guard<std::mutex> lk(ctx->mu);
     for (GraphEntry& g : ctx->graphs)
-      if (same_jobs(g.jobs, jobs, n_jobs)) {
+      if (same_jobs(g, jobs, plans, n_jobs)) {
         hipError_t e = hipGraphLaunch(g.exec, stream);
         return set_hip_error(ctx, e);
       }
@@ -288,6 +316,7 @@ int batch_graph_impl(frntt_ctx* ctx, const frntt_job* jobs, int n_jobs, hipStrea
   // new entry: dedicated scratch and descriptors, captured once
   GraphEntry g;
   g.jobs.assign(jobs, jobs + n_jobs);
+  g.plans = plans;
   hipError_t e;
   if (stot) {
     e = hipMalloc(&g.scratch, stot);

@@ -41,8 +41,14 @@ struct Scratch {
   size_t bytes = 0;
 };
 
+struct JobPlan {
+  int algo = 0;
+  Plan plan;
+};
+
 struct GraphEntry {
   std::vector<frntt_job> jobs;
+  std::vector<JobPlan> plans;  // the form and plan of each job when captured
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   void* dev_buf = nullptr;  // descriptors + counters used by the captured launch
@@ -59,11 +65,6 @@ struct BatchBuffers {
 };
 
 // Algorithm and plan fixed for one job of a batch.
-struct JobPlan {
-  int algo = 0;
-  Plan plan;
-};
-
 struct TuneEntry {
   int algo = FRNTT_ALGO_FOURSTEP_MFMA;
   int n_pass = 0;

@@ -19,11 +19,16 @@ FRNTT_PLAN_KERNELS(FRNTT_BATCH_LDS_OK)
 // constant address space, at a wave-uniform address, so the reads become
 // scalar loads that no store can invalidate (through a plain reference they
 // would be reloaded from memory after every store, inside the pair loops).
+// The address passes through an empty asm statement, so that loads through
+// two references made in different iterations of a loop are not merged and
+// hoisted out of it (that would keep every field live in scalar registers
+// across the whole loop).
 template <class S>
 __device__ FRNTT_INLINE const S& constant_ref(const S& g) {
   const uint64_t a = (uint64_t)(uintptr_t)&g;
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  __asm__ volatile("" : "+s"(lo), "+s"(hi));
   const __attribute__((address_space(4))) S* c =
       (const __attribute__((address_space(4))) S*)(((uint64_t)hi << 32) | lo);
   return *(const S*)c;
@@ -33,29 +38,34 @@ __device__ FRNTT_INLINE const S& constant_ref(const S& g) {
 // loop), so that its registers are allocated for it alone. P and T must be
 // references into global memory (the batch buffer): they are re-read through
 // the constant address space.
+// A call runs the item's `count` consecutive tiles, staging the constant
+// blocks for the first only.
 template <int M0, int M1, int M2>
 __device__ __attribute__((noinline)) void batch_plan_pass(u32x4* lds, i32x4* lds_f, const PassParams& P,
-                                                          const DevTables& T, int64_t wg) {
-  run_pass_plan<M0, M1, M2>(lds, lds_f, constant_ref(P), constant_ref(T), wg);
+                                                          const DevTables& T, int64_t wg, int count) {
+  for (int t = 0; t < count; ++t) run_pass_plan<M0, M1, M2>(lds, lds_f, constant_ref(P), constant_ref(T), wg + t, t == 0);
 }
 
 __device__ __attribute__((noinline)) void batch_bfly_pass(u32x4* lds, const PassParams& P, const DevTables& T,
-                                                          int64_t wg) {
-  run_pass_bfly<kMfmaThreads>(lds, constant_ref(P), constant_ref(T), wg);
+                                                          int64_t wg, int count) {
+  for (int t = 0; t < count; ++t) {
+    run_pass_bfly<kMfmaThreads>(lds, constant_ref(P), constant_ref(T), wg + t);
+    __syncthreads();  // the next tile's loads overwrite the LDS rows this one stored from
+  }
 }
 
 __device__ FRNTT_INLINE void run_batch_pass(u32x4* lds, i32x4* lds_f, const PassParams& P, const DevTables& T,
-                                            int64_t wg) {
+                                            int64_t wg, int count) {
   const int nlev = P.nlev;
   const int code = __builtin_amdgcn_readfirstlane(
       P.engine == 1 ? nlev * 1000 + P.lev_log[0] * 100 + (nlev > 1 ? P.lev_log[1] : 0) * 10 + (nlev > 2 ? P.lev_log[2] : 0)
                     : 0);
   switch (code) {
 #define FRNTT_BATCH_CASE(a, b, c) \
-    case (c > 0 ? 3 : b > 0 ? 2 : 1) * 1000 + a * 100 + b * 10 + c: batch_plan_pass<a, b, c>(lds, lds_f, P, T, wg); return;
+    case (c > 0 ? 3 : b > 0 ? 2 : 1) * 1000 + a * 100 + b * 10 + c: batch_plan_pass<a, b, c>(lds, lds_f, P, T, wg, count); return;
     FRNTT_PLAN_KERNELS(FRNTT_BATCH_CASE)
 #undef FRNTT_BATCH_CASE
-    default: batch_bfly_pass(lds, P, T, wg);
+    default: batch_bfly_pass(lds, P, T, wg, count);
   }
 }
 
@@ -82,7 +92,8 @@ __global__ __launch_bounds__(kMfmaThreads) void ntt_batch_kernel(BatchParams B) 
     const int p = __builtin_amdgcn_readfirstlane((int)B.item_pass[item]);
     const PassParams& P = B.passes[p];  // global memory
     const int64_t wg = B.item_wg[item];
-    run_batch_pass(lds, lds_f, P, *B.tables, wg);
+    const int count = __builtin_amdgcn_readfirstlane(B.item_cnt[item]);
+    run_batch_pass(lds, lds_f, P, *B.tables, wg, count);
     __syncthreads();  // the next fetch rewrites the item slot
   }
 }

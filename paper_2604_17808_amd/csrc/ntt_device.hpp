@@ -74,7 +74,8 @@ struct PassParams {
 struct BatchParams {
   const PassParams* passes;   // all passes of all jobs
   const int64_t* item_pass;   // pass of each work item, items ordered stage by stage
-  const int64_t* item_wg;     // workgroup index of each item inside its pass
+  const int64_t* item_wg;     // first workgroup (tile) of each item inside its pass
+  const int* item_cnt;        // consecutive workgroups (tiles) of each item
   int64_t item_begin;         // this launch's items: [item_begin, item_end)
   int64_t item_end;
   unsigned int* queue;        // this launch's next item (zeroed before the launches)
@@ -164,12 +165,15 @@ __device__ FRNTT_INLINE int64_t logical_wg(const PassParams& P) {
 // Digits k_1..k_{P-1} of the output base `ob` (k_1 least significant) laid
 // out as they sit in the last pass's input (k_1 most significant).
 __device__ FRNTT_INLINE int64_t digit_reverse(const PassParams& P, int64_t ob) {
+  // at most three earlier passes; a pass beyond the plan contributes no digit
+  // (straight-line code, so that callers can keep many elements in flight)
   int64_t kp = 0;
   int d = 0;
   int s = P.log_n - P.pass_log[P.n_pass - 1];  // bits of kp
-  for (int q = 0; q < P.n_pass - 1; ++q) {
-    int l = P.pass_log[q];
-    int64_t k = (ob >> d) & ((1ll << l) - 1);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int l = q < P.n_pass - 1 ? P.pass_log[q] : 0;
+    const int64_t k = (ob >> d) & ((1ll << l) - 1);
     s -= l;
     kp |= k << s;
     d += l;
@@ -187,12 +191,27 @@ struct LineMap {
   int64_t poly_off;  // last pass: offset of k = 0 inside its polynomial
 };
 
+// Element index of input n = 0 of a line: a non-last pass (STRIDED) or the
+// last pass.
+template <bool STRIDED>
+__device__ FRNTT_INLINE int64_t line_in_base(const PassParams& P, int64_t line) {
+  if constexpr (STRIDED) {
+    const int64_t hi = line >> P.log_s;
+    const int64_t rest = line & ((1ll << P.log_s) - 1);
+    return (hi << (P.log_r + P.log_s)) | rest;
+  } else {
+    const int64_t poly = line >> P.log_d;
+    const int64_t ob = line & ((1ll << P.log_d) - 1);
+    const int64_t kp = P.n_pass > 1 ? digit_reverse(P, ob) : 0;
+    return (poly << P.log_n) + (kp << P.log_r);
+  }
+}
+
 __device__ FRNTT_INLINE LineMap map_line(const PassParams& P, int64_t line) {
   LineMap m;
   if (!P.is_last) {
-    int64_t hi = line >> P.log_s;
     int64_t rest = line & ((1ll << P.log_s) - 1);
-    int64_t base = (hi << (P.log_r + P.log_s)) | rest;
+    int64_t base = line_in_base<true>(P, line);
     m.in_base = base;
     m.out_base = base;
     m.in_shift = P.log_s;
@@ -202,8 +221,7 @@ __device__ FRNTT_INLINE LineMap map_line(const PassParams& P, int64_t line) {
   } else {
     int64_t poly = line >> P.log_d;
     int64_t ob = line & ((1ll << P.log_d) - 1);
-    int64_t kp = P.n_pass > 1 ? digit_reverse(P, ob) : 0;
-    m.in_base = (poly << P.log_n) + (kp << P.log_r);
+    m.in_base = line_in_base<false>(P, line);
     m.out_base = (poly << P.log_n) + ob;
     m.in_shift = 0;
     m.out_shift = P.log_d;

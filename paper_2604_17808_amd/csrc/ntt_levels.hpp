@@ -52,36 +52,88 @@ __device__ FRNTT_INLINE void lds_st(u32x4* lds, int e, const fr_t& x) {
 // ------------------------------------------------------ load / store phases
 
 // Stage the workgroup's G lines in LDS at position n * G + line (with the
-// coset pre-scale x_n * g^n in the first pass of a coset transform).
-template <int NT>
-__device__ FRNTT_INLINE void load_lines(u32x4* lds, const PassParams& P, const DevTables& T, int64_t wg) {
+// coset pre-scale x_n * g^n in the first pass of a coset transform). A thread
+// takes U elements at a time: it computes their addresses, issues all their
+// loads (data and coset factors), and only then waits, so a full tile arrives
+// in one memory round trip instead of one per element. STRIDED: a non-last
+// pass, whose pass axis is strided in memory (neighbouring threads take
+// neighbouring lines); in the last pass lines are contiguous and
+// neighbouring threads take neighbouring n. PRE is the pre-scale: 0 none,
+// 1 g^idx from the split tables (two factors per element), 2 the per-line
+// part rides in the pass table and (g^(2^S))^n sits at the table's end.
+template <int NT, int U, int PRE, bool STRIDED>
+__device__ FRNTT_INLINE void load_lines_u(u32x4* lds, const PassParams& P, const DevTables& T, int64_t wg) {
   const int T_el = 1 << P.log_t;
   const int G = 1 << P.log_g;
-  const int tid = threadIdx.x;
   const int64_t nmask = (1ll << P.log_n) - 1;
-  if (!P.is_last) {
-    // pass axis strided: neighbouring threads take neighbouring lines
-    for (int e = tid; e < T_el; e += NT) {
-      const int n = e >> P.log_g, line = e & (G - 1);
-      const LineMap mp = map_line(P, wg * G + line);
-      const int64_t idx = mp.in_base + ((int64_t)n << mp.in_shift);
-      fr_t x = ld_elem(P.src, idx);
-      if (P.coset_pre == 1) x = mont_mul(x, coset_pow(T, 0, (uint32_t)(idx & nmask)));
-      else if (P.coset_pre == 2) x = mont_mul(x, ld_elem(P.pass_tw, (1ll << (P.log_r + P.log_s)) + n));
-      lds_st(lds, e, x);
+  for (int e0 = threadIdx.x; e0 < T_el; e0 += NT * U) {
+    int64_t idx[U];
+    int pos[U], nn[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * NT;
+      int line;
+      if constexpr (STRIDED) {
+        nn[u] = e >> P.log_g;
+        line = e & (G - 1);
+        pos[u] = e;
+      } else {
+        line = e >> P.log_r;
+        nn[u] = e & ((1 << P.log_r) - 1);
+        pos[u] = nn[u] * G + line;
+      }
+      const int64_t base = line_in_base<STRIDED>(P, wg * G + line);
+      idx[u] = base + ((int64_t)nn[u] << (STRIDED ? P.log_s : 0));
     }
-  } else {
-    // lines contiguous in memory: neighbouring threads take neighbouring n
-    const int R = 1 << P.log_r;
-    for (int e = tid; e < T_el; e += NT) {
-      const int line = e >> P.log_r, n = e & (R - 1);
-      const LineMap mp = map_line(P, wg * G + line);
-      const int64_t idx = mp.in_base + n;
-      fr_t x = ld_elem(P.src, idx);
-      if (P.coset_pre) x = mont_mul(x, coset_pow(T, 0, (uint32_t)(idx & nmask)));
-      lds_st(lds, n * G + line, x);
+    fr_t x[U], f0[U], f1[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      x[u] = ld_elem(P.src, idx[u]);
+      if constexpr (PRE == 1) {
+        const uint32_t i = (uint32_t)(idx[u] & nmask);
+        f0[u] = ld_elem(T.g_lo[0], i & ((1u << kSplit) - 1));
+        f1[u] = ld_elem(T.g_hi[0], i >> kSplit);
+      } else if constexpr (PRE == 2) {
+        f0[u] = ld_elem(P.pass_tw, (1ll << (P.log_r + P.log_s)) + nn[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      fr_t y = x[u];
+      if constexpr (PRE == 1) y = mont_mul(y, mont_mul(f0[u], f1[u]));
+      else if constexpr (PRE == 2) y = mont_mul(y, f0[u]);
+      lds_st(lds, pos[u], y);
     }
   }
+}
+
+template <int NT, int U, bool STRIDED>
+__device__ FRNTT_INLINE void load_lines_s(u32x4* lds, const PassParams& P, const DevTables& T, int64_t wg) {
+  // the last pass (a single-pass coset transform) takes g^idx from the split
+  // tables. With a pre-scale product per element the unrolled body grows
+  // large, so fewer elements are kept in flight.
+  const int pre = STRIDED ? P.coset_pre : (P.coset_pre ? 1 : 0);
+  constexpr int U1 = U > 2 ? 2 : 1;
+  if ((1 << P.log_t) < NT * U) {
+    // a tile smaller than NT * U elements: one element per thread at a time
+    if (pre == 0) load_lines_u<NT, 1, 0, STRIDED>(lds, P, T, wg);
+    else if (pre == 2) load_lines_u<NT, 1, 2, STRIDED>(lds, P, T, wg);
+    else load_lines_u<NT, 1, 1, STRIDED>(lds, P, T, wg);
+  } else if (pre == 0) {
+    load_lines_u<NT, U, 0, STRIDED>(lds, P, T, wg);
+  } else if (pre == 2) {
+    load_lines_u<NT, U1, 2, STRIDED>(lds, P, T, wg);
+  } else {
+    load_lines_u<NT, U1, 1, STRIDED>(lds, P, T, wg);
+  }
+}
+
+// NT * U must divide the tile when the tile has at least NT * U elements
+// (both are powers of two).
+template <int NT, int U>
+__device__ FRNTT_INLINE void load_lines(u32x4* lds, const PassParams& P, const DevTables& T, int64_t wg) {
+  if (P.is_last) load_lines_s<NT, U, false>(lds, P, T, wg);
+  else load_lines_s<NT, U, true>(lds, P, T, wg);
 }
 
 // Butterfly engine: write output k of every line (found at LDS row
@@ -333,10 +385,24 @@ __device__ FRNTT_INLINE int level_out_pos(const PassParams& P, const LevelGeom& 
 template <int M, int NT>
 __device__ FRNTT_INLINE void stage_bat(i32x4* dst, const DevTables& T, int dir) {
   constexpr int RHO = 1 << M;
+  // all loads of a thread first, then its LDS stores: one memory round trip
+  constexpr int NB = (RHO * 64 + NT - 1) / NT, NS = (RHO * 8 + NT - 1) / NT;
   const i32x4* bat = T.bat[dir][M];
   const i32x4* seeds = T.bat_init[dir][M];
-  for (int i = threadIdx.x; i < RHO * 64; i += NT) dst[i] = bat[i];
-  for (int i = threadIdx.x; i < RHO * 8; i += NT) dst[RHO * 64 + i] = seeds[i];
+  const int tid = threadIdx.x;
+  i32x4 b[NB], sd[NS];
+#pragma unroll
+  for (int u = 0; u < NB; ++u)
+    if (tid + u * NT < RHO * 64) b[u] = bat[tid + u * NT];
+#pragma unroll
+  for (int u = 0; u < NS; ++u)
+    if (tid + u * NT < RHO * 8) sd[u] = seeds[tid + u * NT];
+#pragma unroll
+  for (int u = 0; u < NB; ++u)
+    if (tid + u * NT < RHO * 64) dst[tid + u * NT] = b[u];
+#pragma unroll
+  for (int u = 0; u < NS; ++u)
+    if (tid + u * NT < RHO * 8) dst[RHO * 64 + tid + u * NT] = sd[u];
 }
 
 template <int M>
@@ -607,13 +673,17 @@ __device__ FRNTT_INLINE void plan_last_level(u32x4* lds, i32x4* blk, const PassP
 
 template <int M0, int M1, int M2>
 __device__ FRNTT_INLINE void run_pass_plan(u32x4* lds, i32x4* lds_f, const PassParams& P, const DevTables& T,
-                                           int64_t wg) {
+                                           int64_t wg, bool stage = true) {
   using PL = PassPlan<M0, M1, M2>;
   constexpr int LT = kMaxLogT;  // staged elements 2^12
-  stage_bat<M0, kMfmaThreads>(lds_f, T, P.dir);
-  if constexpr (PL::kStage1) stage_bat<(M1 > 0 ? M1 : 1), kMfmaThreads>(lds_f + PL::kOff1, T, P.dir);
-  if constexpr (PL::kStage2) stage_bat<(M2 > 0 ? M2 : 1), kMfmaThreads>(lds_f + PL::kOff2, T, P.dir);
-  load_lines<kMfmaThreads>(lds, P, T, wg);
+  // the constant blocks of the pass (a workgroup that runs several tiles of
+  // one pass in a row stages them once)
+  if (stage) {
+    stage_bat<M0, kMfmaThreads>(lds_f, T, P.dir);
+    if constexpr (PL::kStage1) stage_bat<(M1 > 0 ? M1 : 1), kMfmaThreads>(lds_f + PL::kOff1, T, P.dir);
+    if constexpr (PL::kStage2) stage_bat<(M2 > 0 ? M2 : 1), kMfmaThreads>(lds_f + PL::kOff2, T, P.dir);
+  }
+  load_lines<kMfmaThreads, (1 << kMaxLogT) / kMfmaThreads>(lds, P, T, wg);
   __syncthreads();
   if constexpr (M1 == 0) {
     plan_last_level<M0>(lds, lds_f, P, T, level_geom(M0, 0, 0, 0), wg);
@@ -632,7 +702,7 @@ __device__ FRNTT_INLINE void run_pass_plan(u32x4* lds, i32x4* lds_f, const PassP
 // One pass on the butterfly engine with NT threads per workgroup.
 template <int NT>
 __device__ FRNTT_INLINE void run_pass_bfly(u32x4* lds, const PassParams& P, const DevTables& T, int64_t wg) {
-  load_lines<NT>(lds, P, T, wg);
+  load_lines<NT, 2>(lds, P, T, wg);
   __syncthreads();
   bfly_stages<NT>(lds, P, T);
   store_lines<NT>(lds, P, T, wg);
