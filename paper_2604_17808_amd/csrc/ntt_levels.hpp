@@ -536,6 +536,11 @@ struct TileLoop {
       LineMap mp{};
       if (KIND != 1) mp = map_line(P, wg * (1 << P.log_g) + (v & ((1 << P.log_g) - 1)));
       const int64_t rest = mp.rest;
+      // KIND 5: the pass twiddle comes from an HBM table; it is loaded one pair
+      // earlier than the other factors, so that its latency is covered by a
+      // whole pair of MFMAs
+      fr_t tw_next;
+      if (KIND == 5) tw_next = ld_elem(P.pass_tw, ((int64_t)(kk + ((half * NKP) << g.pprev_log)) << P.log_s) + rest);
 #pragma unroll 1
       for (int kp = 0; kp < NKP; ++kp) {
         const int k = kp + half * NKP;  // this lane's output digit: pair kp holds kp and kp + RHO/2
@@ -548,7 +553,10 @@ struct TileLoop {
           wk.tw = ld_elem(Tb.tw_lo[P.dir], E & ((1u << kSplit) - 1));
           wk.tw2 = ld_elem(Tb.tw_hi[P.dir], E >> kSplit);
         }
-        if (KIND == 5) wk.tw = ld_elem(P.pass_tw, ((int64_t)(kk + (k << g.pprev_log)) << P.log_s) + rest);
+        if (KIND == 5) {
+          wk.tw = tw_next;
+          if (kp + 1 < NKP) tw_next = ld_elem(P.pass_tw, ((int64_t)(kk + ((k + 1) << g.pprev_log)) << P.log_s) + rest);
+        }
         if (KIND == 3) wk.tw = ld_elem(Tb.ninv, P.log_n);
         if (KIND == 7) wk.tw = ld_elem(P.post_tw, kk + (k << g.pprev_log));
         if (KIND == 4 || KIND == 6) {
