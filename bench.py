@@ -34,8 +34,8 @@ MADS_PER_MERGE = 32            # carry merge: 24 for the word groups + 8 for the
 PASS_TABLE_MAX_LOG = 25        # the library keeps a twiddle table for non-last passes up to 2^25 entries
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_mfma_fwd_2e20.txt")
 # sources of the profiled kernel: the field arithmetic, the level engine and the
-# translation unit instantiating the <4,3,3> plan kernel of the 2^20 passes
-KERNEL_SOURCES = ["fr.hpp", "ntt_device.hpp", "ntt_levels.hpp", "ntt_plan_c.hip"]
+# translation unit instantiating the <3,4,3> plan kernel of the 2^20 passes
+KERNEL_SOURCES = ["fr.hpp", "ntt_device.hpp", "ntt_levels.hpp", "ntt_plan_h.hip"]
 
 
 def log(msg):
@@ -75,11 +75,13 @@ def settle_clocks(ctx, torch, fr, ptr, log_n, stream, seconds):
 
 def level_split(l, max_m=4):
     """Radices (log2) of the MFMA levels of a pass of radix 2^l with a
-    4096-element tile: fewest levels of at most 2^max_m, as even as possible
+    4096-element tile: fewest levels of at most 2^max_m, as even as possible,
+    larger first except that a three-level split starts with its smallest
     (the library's default split)."""
     n = max(1, -(-l // max_m))
     base, extra = divmod(l, n)
-    return [base + (1 if i < extra else 0) for i in range(n)]
+    levs = [base + (1 if i < extra else 0) for i in range(n)]
+    return levs[-1:] + levs[:-1] if n == 3 else levs
 
 
 def algorithmic_work(plan, kind=0):

@@ -719,9 +719,10 @@ __device__ FRNTT_INLINE void run_pass_bfly(u32x4* lds, const PassParams& P, cons
 // Plan kernels of the matrix form, one per level split of a 4096-element
 // tile (each in a translation unit of its own, so that they compile in
 // parallel), and the dispatcher that finds the one for a split.
-// The first twelve are the default splits of a pass radix 2^12 .. 2^1 (fewest
-// levels of at most 16, larger first); the last four are the other orders of
-// the 2^10 and 2^11 splits, which the autotuner may choose.
+// The first twelve are the splits of a pass radix 2^12 .. 2^1 into the
+// fewest levels of at most 16, larger first; the last four are the other
+// orders of the 2^10 and 2^11 splits. Three-level defaults start with the
+// smallest radix (3,4,3 and 3,4,4); the autotuner may choose any order.
 #define FRNTT_PLAN_KERNELS(X) \
   X(4, 4, 4) X(4, 4, 3) X(4, 3, 3) X(3, 3, 3) X(4, 4, 0) X(4, 3, 0) X(3, 3, 0) X(3, 2, 0) \
   X(4, 0, 0) X(3, 0, 0) X(2, 0, 0) X(1, 0, 0) X(3, 4, 3) X(3, 3, 4) X(3, 4, 4) X(4, 3, 4)

@@ -13,10 +13,11 @@ import bench  # noqa: E402
 
 
 def test_level_split_matches_the_library_rule():
-    # fewest levels of radix <= 16, larger levels first
+    # fewest levels of radix <= 16, larger levels first, except that three
+    # levels start with the smallest
     assert bench.level_split(12) == [4, 4, 4]
-    assert bench.level_split(11) == [4, 4, 3]
-    assert bench.level_split(10) == [4, 3, 3]
+    assert bench.level_split(11) == [3, 4, 4]
+    assert bench.level_split(10) == [3, 4, 3]
     assert bench.level_split(9) == [3, 3, 3]
     assert bench.level_split(8) == [4, 4]
     assert bench.level_split(5) == [3, 2]

@@ -155,19 +155,19 @@ def test_autotuner(ctx, tmp_path):
 
 
 def test_tuned_level_split_single_and_batch(ctx, tmp_path):
-    """A tuned plan with non-default level orders ([3,4,3] and [3,3,4] in the
+    """A tuned plan with non-default level orders ([4,3,3] and [3,3,4] in the
     two 2^10 passes of 2^20) is used by single transforms and by batches, and
     both stay bit-exact."""
     path = str(tmp_path / "tune20.json")
     with open(path, "w") as fh:
         json.dump({"format": "frntt-tune-1", "entries": [
-            {"log_n": 20, "algo": 2, "passes": [10, 10], "ms": 0.1, "levels": [[3, 4, 3], [3, 3, 4]]}]}, fh)
+            {"log_n": 20, "algo": 2, "passes": [10, 10], "ms": 0.1, "levels": [[4, 3, 3], [3, 3, 4]]}]}, fh)
     c = fr.Context(0, max_log_n=20)
     try:
-        assert c.get_plan_levels(fr.ALGO_AUTO, 20, 0) == [4, 3, 3]         # default split
+        assert c.get_plan_levels(fr.ALGO_AUTO, 20, 0) == [3, 4, 3]         # default split
         c.tune_load(path)
         assert c.get_plan(fr.ALGO_AUTO, 20) == [10, 10]
-        assert c.get_plan_levels(fr.ALGO_AUTO, 20, 0) == [3, 4, 3]
+        assert c.get_plan_levels(fr.ALGO_AUTO, 20, 0) == [4, 3, 3]
         assert c.get_plan_levels(fr.ALGO_AUTO, 20, 1) == [3, 3, 4]
         x = si.polynomial(33, 20)
         for kind in (fr.FWD, fr.COSET_INV):
