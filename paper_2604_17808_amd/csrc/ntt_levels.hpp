@@ -381,28 +381,45 @@ __device__ FRNTT_INLINE int level_out_pos(const PassParams& P, const LevelGeom& 
 
 // Constant blocks of radix 2^M (RHO x 64 lanes x 16 B of signed digits)
 // followed by the accumulator seeds (RHO x 2 halves x 16 int32), staged in
-// LDS at dst.
+// LDS: load() issues a thread's loads, store() writes them to LDS (in
+// between, other loads can be issued, whose latency the staging then covers).
+template <int M, int NT>
+struct BatStage {
+  static constexpr int RHO = 1 << M;
+  static constexpr int NB = (RHO * 64 + NT - 1) / NT, NS = (RHO * 8 + NT - 1) / NT;
+  i32x4 b[NB], sd[NS];
+  // slot u of the thread lies below `count` (always, when all NT threads' slots do)
+  __device__ FRNTT_INLINE static bool in_range(int u, int count) {
+    return (u + 1) * NT <= count || (int)threadIdx.x + u * NT < count;
+  }
+  __device__ FRNTT_INLINE void load(const DevTables& T, int dir) {
+    const i32x4* bat = T.bat[dir][M];
+    const i32x4* seeds = T.bat_init[dir][M];
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < NB; ++u)
+      if (in_range(u, RHO * 64)) b[u] = bat[tid + u * NT];
+#pragma unroll
+    for (int u = 0; u < NS; ++u)
+      if (in_range(u, RHO * 8)) sd[u] = seeds[tid + u * NT];
+  }
+  __device__ FRNTT_INLINE void store(i32x4* dst) const {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < NB; ++u)
+      if (in_range(u, RHO * 64)) dst[tid + u * NT] = b[u];
+#pragma unroll
+    for (int u = 0; u < NS; ++u)
+      if (in_range(u, RHO * 8)) dst[RHO * 64 + tid + u * NT] = sd[u];
+  }
+};
+
+// All loads of a thread first, then its LDS stores: one memory round trip.
 template <int M, int NT>
 __device__ FRNTT_INLINE void stage_bat(i32x4* dst, const DevTables& T, int dir) {
-  constexpr int RHO = 1 << M;
-  // all loads of a thread first, then its LDS stores: one memory round trip
-  constexpr int NB = (RHO * 64 + NT - 1) / NT, NS = (RHO * 8 + NT - 1) / NT;
-  const i32x4* bat = T.bat[dir][M];
-  const i32x4* seeds = T.bat_init[dir][M];
-  const int tid = threadIdx.x;
-  i32x4 b[NB], sd[NS];
-#pragma unroll
-  for (int u = 0; u < NB; ++u)
-    if (tid + u * NT < RHO * 64) b[u] = bat[tid + u * NT];
-#pragma unroll
-  for (int u = 0; u < NS; ++u)
-    if (tid + u * NT < RHO * 8) sd[u] = seeds[tid + u * NT];
-#pragma unroll
-  for (int u = 0; u < NB; ++u)
-    if (tid + u * NT < RHO * 64) dst[tid + u * NT] = b[u];
-#pragma unroll
-  for (int u = 0; u < NS; ++u)
-    if (tid + u * NT < RHO * 8) dst[RHO * 64 + tid + u * NT] = sd[u];
+  BatStage<M, NT> s;
+  s.load(T, dir);
+  s.store(dst);
 }
 
 template <int M>
@@ -515,18 +532,30 @@ __device__ FRNTT_INLINE void mfma_pair_work(const i32x4* lds_f, const i32x4* ini
   DigitLoop<RHO, WORKING, W, 0>::run(lds_f, Bt, k0, lane, e, o, wk, a);
 }
 
+// Unsigned data bytes u -> signed u - 128 (the seeds carry 128 times the
+// digit sums).
+template <int RHO>
+__device__ FRNTT_INLINE void to_signed(i32x4 (&b)[RHO]) {
+#pragma unroll
+  for (int n = 0; n < RHO; ++n) b[n] = (i32x4)((u32x4)b[n] ^ 0x80808080u);
+}
+
 // The output pairs of tile T of a wave (tiles unrolled at compile time, so
 // every data-fragment index is static): pair kp is finished while the MFMAs
-// of the next pair (of this tile, or the first of the next) run.
-template <int M, int TPW, int KIND, int T>
+// of the next pair (of this tile, or the first of the next) run. RAW: the
+// fragments of later tiles still hold unsigned bytes straight from HBM; the
+// next tile's are converted when this one starts, so that the wait for
+// their loads falls after this tile's first MFMAs.
+template <int M, int TPW, int KIND, int T, bool RAW>
 struct TileLoop {
   __device__ FRNTT_INLINE static void run(u32x4* lds, const i32x4* lds_f, const i32x4* init, const PassParams& P,
-                                          const DevTables& Tb, const LevelGeom& g, const i32x4 (&B)[TPW][1 << M],
+                                          const DevTables& Tb, const LevelGeom& g, i32x4 (&B)[TPW][1 << M],
                                           int tile0, int col, int half, int lane, int64_t wg, i32x16& n0,
                                           i32x16& n1, PairWork<KIND>& wk) {
     if constexpr (T < TPW) {
       constexpr int RHO = 1 << M;
       constexpr int NKP = RHO / 2;
+      if constexpr (RAW && T + 1 < TPW) to_signed<RHO>(B[T + 1]);
       const int v = (tile0 + T) * 32 + col;
       const int rem = v >> P.log_g;
       const int nn = rem >> g.pprev_log;                 // KIND 1: the vector's twiddle row
@@ -582,9 +611,14 @@ struct TileLoop {
           st_elem(P.dst, mp.out_base + ((int64_t)(kk + (k << g.pprev_log)) << mp.out_shift), y);
         }
       }
-      TileLoop<M, TPW, KIND, T + 1>::run(lds, lds_f, init, P, Tb, g, B, tile0, col, half, lane, wg, n0, n1, wk);
+      TileLoop<M, TPW, KIND, T + 1, RAW>::run(lds, lds_f, init, P, Tb, g, B, tile0, col, half, lane, wg, n0, n1, wk);
     }
   }
+};
+
+// Nothing to stage (the constant blocks are in LDS already).
+struct NoStage {
+  __device__ FRNTT_INLINE void store() const {}
 };
 
 // One MFMA level. The 2^(log_t - m) vectors form tiles of 32; each of the 8
@@ -596,9 +630,18 @@ struct TileLoop {
 // inter-level or pass twiddle and written to the position the next level
 // reads, or, in the last level, straight to its place in HBM (KIND: see
 // PairWork).
-template <int M, int TPW, int KIND>
+//
+// HBM: the first level of a pass without a pre-scale reads its fragments
+// straight from the pass's input instead of from a tile staged in LDS, so
+// that no load phase precedes the MFMAs: a wave issues all its fragment
+// loads, then `st` writes the constant blocks whose loads were issued before
+// (covering part of the fragments' latency), and the first pair waits only
+// for the first tile's fragments. Input digit n of vector v = (n_low, line)
+// is element n * R / rho + n_low of the line, which the staged tile would
+// have held at row n of vector v.
+template <int M, int TPW, int KIND, bool HBM = false, class ST = NoStage>
 __device__ FRNTT_INLINE void mfma_level(u32x4* lds, i32x4* blk, const PassParams& P, const DevTables& T,
-                                        const LevelGeom& g, bool stage, int64_t wg) {
+                                        const LevelGeom& g, bool stage, int64_t wg, const ST& st = ST()) {
   constexpr int RHO = 1 << M;
   constexpr int NKP = RHO / 2;  // output pairs per tile
   const int V = 1 << (P.log_t - M);
@@ -613,16 +656,38 @@ __device__ FRNTT_INLINE void mfma_level(u32x4* lds, i32x4* blk, const PassParams
   const i32x4* lds_f = blk;
   const i32x4* init = blk + RHO * 64;
   i32x4 B[TPW][RHO];
+  if constexpr (HBM) {
+    const int G = 1 << P.log_g;
+    const int row_log = P.log_r - M;  // log2 of R / rho
+    const int shift = P.is_last ? 0 : P.log_s;
 #pragma unroll
-  for (int t = 0; t < TPW; ++t) {
-    const int v = (tile0 + t) * 32 + col;
+    for (int t = 0; t < TPW; ++t) {
+      const int v = (tile0 + t) * 32 + col;
+      const int line = v & (G - 1);
+      const int n_low = v >> P.log_g;
+      const int64_t l = wg * G + line;
+      const int64_t base = P.is_last ? line_in_base<false>(P, l) : line_in_base<true>(P, l);
 #pragma unroll
-    for (int n = 0; n < RHO; ++n) {
-      const u32x4 raw = lds[2 * (n * V + v) + half];
-      B[t][n] = (i32x4)(raw ^ 0x80808080u);  // unsigned byte u -> signed u - 128
+      for (int n = 0; n < RHO; ++n) {
+        const int64_t idx = base + ((int64_t)((n << row_log) + n_low) << shift);
+        B[t][n] = (i32x4)P.src[2 * idx + half];
+      }
     }
+    st.store();
+    __syncthreads();
+    to_signed<RHO>(B[0]);
+  } else {
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      const int v = (tile0 + t) * 32 + col;
+#pragma unroll
+      for (int n = 0; n < RHO; ++n) {
+        const u32x4 raw = lds[2 * (n * V + v) + half];
+        B[t][n] = (i32x4)(raw ^ 0x80808080u);  // unsigned byte u -> signed u - 128
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
   PairWork<KIND> wk;
   wk.mg.w1 = T.byte_w[3];
   wk.mg.w8 = T.byte_w[0];
@@ -630,14 +695,14 @@ __device__ FRNTT_INLINE void mfma_level(u32x4* lds, i32x4* blk, const PassParams
   wk.mg.w24 = T.byte_w[2];
   i32x16 n0, n1;
   mfma_pair_work<RHO, false>(lds_f, init, B[0], 0, lane, half, n0, n1, wk);
-  TileLoop<M, TPW, KIND, 0>::run(lds, lds_f, init, P, T, g, B, tile0, col, half, lane, wg, n0, n1, wk);
+  TileLoop<M, TPW, KIND, 0, HBM>::run(lds, lds_f, init, P, T, g, B, tile0, col, half, lane, wg, n0, n1, wk);
   __syncthreads();
 }
 
-// A pass of the matrix form (staged tile of 4096 elements) whose levels are
-// known at compile time: radices 2^M0, then 2^M1 if M1 > 0, then 2^M2 if
-// M2 > 0. The constant blocks of its (at most two) distinct radices are staged
-// once, together with the tile's HBM loads, and every level shape is fixed.
+// A pass of the matrix form (tile of 4096 elements) whose levels are known
+// at compile time: radices 2^M0, then 2^M1 if M1 > 0, then 2^M2 if M2 > 0.
+// The constant blocks of its (at most two) distinct radices are staged once,
+// together with the tile's HBM loads, and every level shape is fixed.
 template <int M0, int M1, int M2>
 struct PassPlan {
   static constexpr int kLevels = M2 > 0 ? 3 : M1 > 0 ? 2 : 1;
@@ -679,24 +744,63 @@ __device__ FRNTT_INLINE void plan_last_level(u32x4* lds, i32x4* blk, const PassP
   else mfma_level<M, TPW, 0>(lds, blk, P, T, g, false, wg);
 }
 
+// The constant blocks of a pass's distinct radices, loaded before the first
+// level's fragment loads are issued and stored to LDS after them (nothing if
+// `on` is false: a workgroup running several tiles of one pass in a row
+// stages them once).
+template <int M0, int M1, int M2>
+struct PlanStage {
+  using PL = PassPlan<M0, M1, M2>;
+  BatStage<M0, kMfmaThreads> s0;
+  BatStage<(M1 > 0 ? M1 : 1), kMfmaThreads> s1;
+  BatStage<(M2 > 0 ? M2 : 1), kMfmaThreads> s2;
+  i32x4* dst;
+  bool on;
+  __device__ FRNTT_INLINE void load(const DevTables& T, int dir) {
+    if (!on) return;
+    s0.load(T, dir);
+    if constexpr (PL::kStage1) s1.load(T, dir);
+    if constexpr (PL::kStage2) s2.load(T, dir);
+  }
+  __device__ FRNTT_INLINE void store() const {
+    if (!on) return;
+    s0.store(dst);
+    if constexpr (PL::kStage1) s1.store(dst + PL::kOff1);
+    if constexpr (PL::kStage2) s2.store(dst + PL::kOff2);
+  }
+};
+
 template <int M0, int M1, int M2>
 __device__ FRNTT_INLINE void run_pass_plan(u32x4* lds, i32x4* lds_f, const PassParams& P, const DevTables& T,
                                            int64_t wg, bool stage = true) {
   using PL = PassPlan<M0, M1, M2>;
   constexpr int LT = kMaxLogT;  // staged elements 2^12
-  // the constant blocks of the pass (a workgroup that runs several tiles of
-  // one pass in a row stages them once)
-  if (stage) {
-    stage_bat<M0, kMfmaThreads>(lds_f, T, P.dir);
-    if constexpr (PL::kStage1) stage_bat<(M1 > 0 ? M1 : 1), kMfmaThreads>(lds_f + PL::kOff1, T, P.dir);
-    if constexpr (PL::kStage2) stage_bat<(M2 > 0 ? M2 : 1), kMfmaThreads>(lds_f + PL::kOff2, T, P.dir);
-  }
-  load_lines<kMfmaThreads, (1 << kMaxLogT) / kMfmaThreads>(lds, P, T, wg);
-  __syncthreads();
   if constexpr (M1 == 0) {
+    if (stage) stage_bat<M0, kMfmaThreads>(lds_f, T, P.dir);
+    load_lines<kMfmaThreads, (1 << kMaxLogT) / kMfmaThreads>(lds, P, T, wg);
+    __syncthreads();
     plan_last_level<M0>(lds, lds_f, P, T, level_geom(M0, 0, 0, 0), wg);
   } else {
-    mfma_level<M0, (1 << (LT - M0 - 8)), 1>(lds, lds_f, P, T, level_geom(M0, 0, M1 + M2, M1), false, wg);
+    constexpr int TPW0 = 1 << (LT - M0 - 8);
+    const LevelGeom g0 = level_geom(M0, 0, M1 + M2, M1);
+    if (P.coset_pre == 0) {
+      // the first level reads its fragments from HBM
+      PlanStage<M0, M1, M2> st;
+      st.dst = lds_f;
+      st.on = stage;
+      st.load(T, P.dir);
+      mfma_level<M0, TPW0, 1, true>(lds, lds_f, P, T, g0, false, wg, st);
+    } else {
+      // the coset pre-scale is applied while the tile is staged in LDS
+      if (stage) {
+        stage_bat<M0, kMfmaThreads>(lds_f, T, P.dir);
+        if constexpr (PL::kStage1) stage_bat<(M1 > 0 ? M1 : 1), kMfmaThreads>(lds_f + PL::kOff1, T, P.dir);
+        if constexpr (PL::kStage2) stage_bat<(M2 > 0 ? M2 : 1), kMfmaThreads>(lds_f + PL::kOff2, T, P.dir);
+      }
+      load_lines<kMfmaThreads, (1 << kMaxLogT) / kMfmaThreads>(lds, P, T, wg);
+      __syncthreads();
+      mfma_level<M0, TPW0, 1>(lds, lds_f, P, T, g0, false, wg);
+    }
     if constexpr (M2 > 0) {
       mfma_level<M1, (1 << (LT - M1 - 8)), 1>(lds, lds_f + PL::kOff1, P, T, level_geom(M1, M0, M2, M2), false, wg);
       plan_last_level<M2>(lds, lds_f + PL::kOff2, P, T, level_geom(M2, M0 + M1, 0, 0), wg);
