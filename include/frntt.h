@@ -218,6 +218,46 @@ int frntt_prepare(frntt_ctx *ctx, int log_n, int kind);
  * tables built so far. */
 size_t frntt_table_bytes(const frntt_ctx *ctx);
 
+/* ---- RNS lazy modular product (paper: Arithmetic Optimizations, the
+ * walk-through example and Alg. 1, "MXU RNS Lazy") ----
+ * A field element x in [0, r) is carried in the extended non-prime ring Z_Q,
+ * Q = q_0 ... q_16 > 2 r^2, as its residues x z mod q_i (z = 2^32,
+ * "Montgomery form" of each residue). The product of two such elements is a
+ * residue-wise 32-bit Montgomery product followed by Alg. 1's Main (one int8
+ * matrix product of the residues' bytes with the BAT constant table, fused
+ * with the overflow-count rows f; then per output residue the byte merge,
+ * + k g_j and the reduction mod p_j), which leaves the lazily reduced product
+ * W' (W' = a b mod r, |W'| < 2^15 r) in a second base P = p_0 ... p_8 as the
+ * residues W' z mod p_j. The moduli are the 26 consecutive primes below
+ * 2^31 - 2^24, the largest 17 forming Q, the next 9 forming P. Tables are
+ * built at context creation.
+ *
+ * Layouts (device memory, 16-byte aligned, element-major):
+ *   canonical: 8 little-endian 32-bit words per element (< r);
+ *   base Q:    FRNTT_RNS_Q_WORDS words per element: residues 0..16, then zeros;
+ *   base P:    FRNTT_RNS_P_WORDS words per element: residues 0..8, then zeros.
+ * Every call is enqueued on `stream` and returns at once; n = 0 is a no-op.
+ * Errors: EINVAL (null context or pointer, n < 0), EALIGN, EHIP. Inputs
+ * outside the documented ranges give unspecified outputs. */
+#define FRNTT_RNS_Q_WORDS 20
+#define FRNTT_RNS_P_WORDS 12
+/* The moduli q_0..q_16 and p_0..p_8 (host only; needs no device). */
+int frntt_rns_moduli(uint32_t *q, uint32_t *p);
+/* Canonical values -> base-Q residues x z mod q_i (the RNS decomposition,
+ * itself one byte matrix product with the bytes of z 2^(8b) mod q_i). */
+int frntt_rns_encode(frntt_ctx *ctx, const void *a, void *xq, int64_t n, void *stream);
+/* Base-Q residues of a and b -> base-P residues of the lazily reduced
+ * product (residue-wise Montgomery product, then Alg. 1 Main). */
+int frntt_rns_mul(frntt_ctx *ctx, const void *xa, const void *xb, void *xp, int64_t n, void *stream);
+/* Base-P residues W' z mod p_j (|W'| < P / 2) -> canonical W' mod r (the RNS
+ * reconstruction: Alg. 1 Main once more, from base P into the 32 bytes of a
+ * 256-bit word, with k rounded to the nearest integer). */
+int frntt_rns_decode(frntt_ctx *ctx, const void *xp, void *out, int64_t n, void *stream);
+/* The radix Montgomery product on the vector ALUs, the baseline of the
+ * paper's arithmetic ablation: out = a b 2^-261 mod r for canonical a, b
+ * (nine 29-bit limbs). */
+int frntt_mont_mul(frntt_ctx *ctx, const void *a, const void *b, void *out, int64_t n, void *stream);
+
 /* Last hipError_t seen by the context (0 if none). */
 int frntt_last_hip_error(const frntt_ctx *ctx);
 /* Static description of a status code. */

@@ -514,6 +514,7 @@ int frntt_ctx_create(frntt_ctx** out, int hip_device, int max_log_n, unsigned fl
   if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess) ctx->cu_count = prop.multiProcessorCount;
   if (ctx->cu_count <= 0) ctx->cu_count = 256;
   int rc = build_tables(ctx);
+  if (rc == FRNTT_OK) rc = build_rns_tables(ctx);
   if (rc == FRNTT_OK && noalloc_scratch_address(&ctx->noalloc_scratch) != 0) rc = FRNTT_EHIP;
   if (rc == FRNTT_OK) {
     hipError_t e = hipMalloc((void**)&ctx->valid_flag, 256);
@@ -548,6 +549,7 @@ int frntt_ctx_destroy(frntt_ctx* ctx) {
     }
     if (ctx->valid_flag) hipFree(ctx->valid_flag);
     if (ctx->table_mem) hipFree(ctx->table_mem);
+    if (ctx->rns_mem) hipFree(ctx->rns_mem);
     for (auto& kv : ctx->pass_tw) hipFree(kv.second);
   }
   delete ctx;

@@ -10,6 +10,7 @@
 
 #include "../../include/frntt.h"
 #include "ntt_device.hpp"
+#include "rns_lazy.hpp"
 
 namespace frntt {
 
@@ -88,6 +89,8 @@ struct frntt_ctx {
   frntt::DevTables tables{};
   unsigned int* valid_flag = nullptr;  // device flag for FRNTT_VALIDATE
   void* noalloc_scratch = nullptr;     // this device's static scratch of ntt_transform_noalloc
+  void* rns_mem = nullptr;             // operand tables of the RNS lazy product
+  frntt::RnsTables rns{};
   // plan overrides [algo][log_n]
   frntt::Plan plan_override[3][29];
   bool has_override[3][29] = {};
@@ -105,6 +108,8 @@ struct frntt_ctx {
 namespace frntt {
 
 int set_hip_error(const frntt_ctx* ctx, hipError_t e);
+// Operand tables of the RNS lazy product (built at context creation).
+int build_rns_tables(frntt_ctx* ctx);
 // Default or overridden plan for (algo, log_n); algo must be BUTTERFLY or MFMA.
 // Takes ctx->mu.
 Plan plan_for(const frntt_ctx* ctx, int algo, int log_n);

@@ -72,9 +72,25 @@ SIGNATURES = {
                                 ctypes.POINTER(_u64)]),
     "frntt_server_peak_inflight": (_i, [_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64)]),
     "frntt_server_destroy": (_i, [_vp]),
+    "frntt_rns_moduli": (_i, [ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32)]),
+    "frntt_rns_encode": (_i, [_vp, _vp, _vp, ctypes.c_int64, _vp]),
+    "frntt_rns_mul": (_i, [_vp, _vp, _vp, _vp, ctypes.c_int64, _vp]),
+    "frntt_rns_decode": (_i, [_vp, _vp, _vp, ctypes.c_int64, _vp]),
+    "frntt_mont_mul": (_i, [_vp, _vp, _vp, _vp, ctypes.c_int64, _vp]),
 }
 
+RNS_Q_WORDS = 20
+RNS_P_WORDS = 12
+
 _lib = None
+
+
+def rns_moduli():
+    """(q_0..q_16, p_0..p_8) of the RNS lazy product (host only)."""
+    q = (ctypes.c_uint32 * 17)()
+    p = (ctypes.c_uint32 * 9)()
+    _check(lib().frntt_rns_moduli(q, p), "frntt_rns_moduli")
+    return list(q), list(p)
 
 
 def library_path() -> str:
@@ -219,6 +235,19 @@ class Context:
 
     def table_bytes(self) -> int:
         return lib().frntt_table_bytes(self._h)
+
+    # RNS lazy modular product (pointers to device memory, n elements)
+    def rns_encode(self, a: int, xq: int, n: int, stream: int = 0):
+        return _check(lib().frntt_rns_encode(self._h, a, xq, n, stream), "frntt_rns_encode")
+
+    def rns_mul(self, xa: int, xb: int, xp: int, n: int, stream: int = 0):
+        return _check(lib().frntt_rns_mul(self._h, xa, xb, xp, n, stream), "frntt_rns_mul")
+
+    def rns_decode(self, xp: int, out: int, n: int, stream: int = 0):
+        return _check(lib().frntt_rns_decode(self._h, xp, out, n, stream), "frntt_rns_decode")
+
+    def mont_mul(self, a: int, b: int, out: int, n: int, stream: int = 0):
+        return _check(lib().frntt_mont_mul(self._h, a, b, out, n, stream), "frntt_mont_mul")
 
     def check_inputs(self) -> int:
         return lib().frntt_check_inputs(self._h)
