@@ -253,6 +253,75 @@ def bench_f1(ctx, torch, fr, stream, steps):
     return out
 
 
+def time_op(torch, fn, steps, warmup):
+    """Mean milliseconds of `fn` (which enqueues on the current stream) over
+    `steps` back-to-back calls between two events, after `warmup` calls."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+# RNS lazy product (Alg. 1): per element, the int8 MFMA work of Main (2 row
+# blocks x 3 K steps of 32x32x32 per 32 elements) and the HBM bytes of each
+# call (base Q: 20 words, base P: 12 words, canonical: 8 words)
+RNS_MUL_OPS = 2 * 3 * 2 * 32 * 32 * 32 // 32
+RNS_BYTES = {"encode": 32 + 80, "mul": 2 * 80 + 48, "decode": 48 + 32, "mont_mul": 3 * 32}
+
+
+def bench_f2(ctx, torch, fr, stream, steps):
+    """The RNS lazy modular product against the radix Montgomery product on the
+    VALUs (the paper's arithmetic ablation) at batch sizes 2^20, 2^22, 2^24:
+    elements per second of each call and of the whole canonical-to-canonical
+    pipeline (two encodes, the product, one decode), with the HBM bandwidth
+    each call reaches and the int8 MFMA rate of the product."""
+    out = {}
+    for log_n in (20, 22, 24):
+        n = 1 << log_n
+        a = torch.empty((n, 4), dtype=torch.int64, device="cuda:0")
+        b = torch.empty_like(a)
+        ctx.generate(a.data_ptr(), 8, 0, 0, n, stream)
+        ctx.generate(b.data_ptr(), 8, 1, 0, n, stream)
+        xa = torch.empty((n * fr.RNS_Q_WORDS,), dtype=torch.int32, device="cuda:0")
+        xb = torch.empty_like(xa)
+        xp = torch.empty((n * fr.RNS_P_WORDS,), dtype=torch.int32, device="cuda:0")
+        o = torch.empty_like(a)
+        ops = {
+            "encode": lambda: ctx.rns_encode(a.data_ptr(), xa.data_ptr(), n, stream),
+            "mul": lambda: ctx.rns_mul(xa.data_ptr(), xb.data_ptr(), xp.data_ptr(), n, stream),
+            "decode": lambda: ctx.rns_decode(xp.data_ptr(), o.data_ptr(), n, stream),
+            "mont_mul": lambda: ctx.mont_mul(a.data_ptr(), b.data_ptr(), o.data_ptr(), n, stream),
+        }
+        ctx.rns_encode(b.data_ptr(), xb.data_ptr(), n, stream)
+        row = {}
+        for name, fn in ops.items():
+            log(f"f2: 2^{log_n} {name}")
+            t = time_op(torch, fn, steps, 2) * 1e-3
+            row[name] = {"us": round(t * 1e6, 2), "melem_s": round(n / t / 1e6, 1),
+                         "hbm_gbs": round(n * RNS_BYTES[name] / t / 1e9, 1)}
+        row["mul"]["mfma_tops"] = round(n * RNS_MUL_OPS / (row["mul"]["us"] * 1e-6) / 1e12, 2)
+
+        def pipeline():
+            ops["encode"]()
+            ctx.rns_encode(b.data_ptr(), xb.data_ptr(), n, stream)
+            ops["mul"]()
+            ops["decode"]()
+        t = time_op(torch, pipeline, steps, 2) * 1e-3
+        row["pipeline"] = {"us": round(t * 1e6, 2), "melem_s": round(n / t / 1e6, 1)}
+        row["mul_over_mont"] = round(row["mont_mul"]["us"] / row["mul"]["us"], 3)
+        out[f"2e{log_n}"] = row
+        del a, b, xa, xb, xp, o
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_c4(ctx, torch, fr, stream, replays):
     """256 forward NTTs, sizes uniform over 2^12..2^20 (seed 4): tune every
     size, capture the persistent batch launch in a hipGraph, time replays."""
@@ -370,8 +439,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing on host cores")
     ap.add_argument("--quick", action="store_true", help="headline config only")
-    ap.add_argument("--only", default="c3,c4,c5,f1",
-                    help="comma list of the other configurations to run (c3, c4, c5, f1)")
+    ap.add_argument("--only", default="c3,c4,c5,f1,f2",
+                    help="comma list of the other configurations to run (c3, c4, c5, f1, f2)")
     ap.add_argument("--c4-replays", type=int, default=200)
     ap.add_argument("--calib", action="store_true",
                     help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
@@ -457,6 +526,8 @@ def main():
 
     if "f1" in extra:
         out["f1"] = bench_f1(ctx, torch, fr, stream, max(3, args.steps // 10))
+    if "f2" in extra:
+        out["f2"] = bench_f2(ctx, torch, fr, stream, max(5, args.steps // 4))
     if "c4" in extra:
         out["c4"] = bench_c4(ctx, torch, fr, stream, args.c4_replays)
     if "c5" in extra:

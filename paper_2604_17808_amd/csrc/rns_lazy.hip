@@ -428,6 +428,20 @@ __device__ FRNTT_INLINE int64_t row_group(const i32x16& a, int g) {
 }
 
 __device__ FRNTT_INLINE uint32_t sel(int half, uint32_t a0, uint32_t a1) { return half ? a1 : a0; }
+
+// Lane halves hold residues 8m + 2 gi + half (gi < 4) of one element in r[gi].
+// Two exchanges with the partner lane give half 0 the residues 8m .. 8m + 3
+// and half 1 the residues 8m + 4 .. 8m + 7, each stored as one 16-byte word
+// group at dst (= the element's word 8m). All lanes take part in the
+// exchanges; `store` masks the write.
+__device__ FRNTT_INLINE void store_block(uint32_t* dst, const uint32_t (&r)[4], int half, bool store) {
+  const uint32_t x1 = __shfl_xor(half ? r[0] : r[2], 32, 64);  // half 0 gets 8m+1, half 1 gets 8m+4
+  const uint32_t x2 = __shfl_xor(half ? r[1] : r[3], 32, 64);  // half 0 gets 8m+3, half 1 gets 8m+6
+  if (store) {
+    if (half == 0) *(u32x4*)dst = u32x4{r[0], x1, r[1], x2};
+    else *(u32x4*)(dst + 4) = u32x4{x1, r[2], x2, r[3]};
+  }
+}
 __device__ FRNTT_INLINE double seld(int half, double a0, double a1) { return half ? a1 : a0; }
 
 }  // namespace
@@ -453,22 +467,23 @@ __global__ __launch_bounds__(kRnsThreads) void rns_encode_kernel(const u32x4* a,
     i32x16 acc[3];
 #pragma unroll
     for (int rb = 0; rb < 3; ++rb) acc[rb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[rb], B, S[rb], 0, 0, 0);
-    if (e < n) {
-      uint32_t* out = xq + e * kRnsQWords;
+    // residues 8 rb + 2 gi + half of this lane's element; the two halves swap
+    // two of them per block so that each stores four consecutive words
+    uint32_t* out = xq + e * kRnsQWords;
 #pragma unroll
-      for (int rb = 0; rb < 3; ++rb)
+    for (int rb = 0; rb < 2; ++rb) {
+      uint32_t r[4];
 #pragma unroll
-        for (int gi = 0; gi < 4; ++gi) {
-          const int j0 = 8 * rb + 2 * gi;  // residue of this group in the half-0 lanes (j0 + 1 in half 1)
-          if (j0 >= kRnsQWords) continue;
-          const int j = j0 + half;
-          if (j0 + 1 < kRnsI || (j0 < kRnsI && half == 0)) {
-            const uint32_t qj = sel(half, T.c.q[j0], T.c.q[j0 + 1]);
-            out[j] = mod_small(row_group(acc[rb], gi), qj, seld(half, T.c.qinv[j0], T.c.qinv[j0 + 1]));
-          } else if (j < kRnsQWords) {
-            out[j] = 0u;  // padding words
-          }
-        }
+      for (int gi = 0; gi < 4; ++gi) {
+        const int j0 = 8 * rb + 2 * gi;
+        r[gi] = mod_small(row_group(acc[rb], gi), sel(half, T.c.q[j0], T.c.q[j0 + 1]),
+                          seld(half, T.c.qinv[j0], T.c.qinv[j0 + 1]));
+      }
+      store_block(out + 8 * rb, r, half, e < n);
+    }
+    if (e < n && half == 0) {
+      const uint32_t r16 = mod_small(row_group(acc[2], 0), T.c.q[16], T.c.qinv[16]);
+      *(u32x4*)(out + 16) = u32x4{r16, 0u, 0u, 0u};
     }
   }
 }
@@ -525,15 +540,17 @@ __global__ __launch_bounds__(kRnsThreads) void rns_mul_kernel(const uint32_t* xa
     const int32_t k_own = (int32_t)(v >> kRnsU);
     const int32_t k_other = __shfl_xor(k_own, 32, 64);
     const int64_t k = half ? k_own : k_other;
-    if (e < n) {
-      uint32_t* out = xp + e * kRnsPWords;
+    uint32_t* out = xp + e * kRnsPWords;
+    uint32_t r[4];
 #pragma unroll
-      for (int gi = 0; gi < 4; ++gi) {
-        const int j0 = 2 * gi;
-        const uint32_t pj = sel(half, T.c.p[j0], T.c.p[j0 + 1]);
-        const uint32_t gj = sel(half, T.c.g[j0], T.c.g[j0 + 1]);
-        out[j0 + half] = mod_small(row_group(acc[0], gi) + k * gj, pj, seld(half, T.c.pinv[j0], T.c.pinv[j0 + 1]));
-      }
+    for (int gi = 0; gi < 4; ++gi) {
+      const int j0 = 2 * gi;
+      const uint32_t pj = sel(half, T.c.p[j0], T.c.p[j0 + 1]);
+      const uint32_t gj = sel(half, T.c.g[j0], T.c.g[j0 + 1]);
+      r[gi] = mod_small(row_group(acc[0], gi) + k * gj, pj, seld(half, T.c.pinv[j0], T.c.pinv[j0 + 1]));
+    }
+    store_block(out, r, half, e < n);
+    if (e < n) {
       if (half == 0) {
         const uint32_t r8 = mod_small(row_group(acc[1], 0) + k * T.c.g[8], T.c.p[8], T.c.pinv[8]);
         *(u32x4*)(out + 8) = u32x4{r8, 0u, 0u, 0u};
