@@ -69,6 +69,30 @@ def test_server_mix_matches_oracle_and_alone(ctx):
         srv.close()
 
 
+def test_server_two_pass_plan_at_2e12():
+    """A 2^12 request under a two-pass plan needs a scratch region although
+    its size fits one tile; the server sizes it from the plan that runs."""
+    c = fr.Context(0, max_log_n=14)
+    try:
+        for algo in (fr.ALGO_FOURSTEP_MFMA, fr.ALGO_BUTTERFLY):
+            c.set_plan(algo, 12, [6, 6])
+        srv = fr.Server(c, 1 << 30, slots=2)
+        try:
+            kinds = [fr.FWD, fr.INV, fr.COSET, fr.COSET_INV] * 3
+            tickets = [srv.submit(k, 12, 9) for k in kinds]
+            srv.drain(60)
+            for k, tk in zip(kinds, tickets):
+                got = fetch(srv, tk, 12)
+                x = si.polynomial(9, 12, stream=tk)
+                assert np.array_equal(got, cref.transform(x, 12, k)), (tk, k)
+        finally:
+            srv.close()
+        assert c.get_plan(fr.ALGO_FOURSTEP_MFMA, 12) == [6, 6]
+    finally:
+        torch.cuda.synchronize()
+        c.close()
+
+
 def test_server_release_on_done(ctx):
     srv = fr.Server(ctx, 1 << 30, slots=2)
     try:
