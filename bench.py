@@ -30,7 +30,9 @@ INT8_PEAK_TOPS = 5000.0        # MI355X dense int8 MFMA, TOP/s (published)
 # published figure: it is measured live by the saturating kernel of
 # libfrntt_peaks.so (256 workgroups, 1..4 waves per SIMD, the best rate).
 MADS_PER_PRODUCT = 162         # Montgomery product on nine 29-bit limbs (9 rows x 18)
+MADS_PER_SHOUP = 154           # inter-level Shoup product: 64 quotient + 45 + 45 low columns
 MADS_PER_MERGE = 32            # carry merge: 24 for the word groups + 8 for the quotient step
+MADS_PER_MERGE_UNREDUCED = 24  # a merge feeding a Shoup product skips the quotient step
 PASS_TABLE_MAX_LOG = 25        # the library keeps a twiddle table for non-last passes up to 2^25 entries
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_mfma_fwd_2e20.txt")
 # sources of the profiled kernel: the field arithmetic, the level engine and the
@@ -94,7 +96,9 @@ def algorithmic_work(plan, kind=0):
     folded = len(plan) > 1 and sum(plan) <= PASS_TABLE_MAX_LOG
     for p, l in enumerate(plan):
         levs = level_split(l)
-        mads = MADS_PER_MERGE * len(levs) + MADS_PER_PRODUCT * (len(levs) - 1)
+        # every level merges; all but the last feed an inter-level Shoup product
+        # with their unreduced sum
+        mads = MADS_PER_MERGE + (MADS_PER_MERGE_UNREDUCED + MADS_PER_SHOUP) * (len(levs) - 1)
         if p + 1 < len(plan):
             # pass twiddle: read from the pass table (one product), or formed
             # from the split tables (two products) above the table size limit

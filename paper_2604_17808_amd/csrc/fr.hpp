@@ -126,12 +126,6 @@ struct MontMul {
     to_limbs29(a, al);
     to_limbs29(b, bl);
   }
-  // a given as its nine 29-bit limbs (a table entry kept in that form)
-  __device__ FRNTT_INLINE void load(const uint32_t* a_limbs, const fr_t& b) {
-#pragma unroll
-    for (int k = 0; k < 9; ++k) al[k] = a_limbs[k];
-    to_limbs29(b, bl);
-  }
   __device__ FRNTT_INLINE void row(int i) {
     if (i == 0) {
 #pragma unroll
@@ -177,6 +171,118 @@ struct MontMul {
       o.w[i] = v;
     }
     return o;
+  }
+};
+
+// Product y w mod r of an unreduced y < 2^290 and a constant w < r by
+// Shoup's method (multiplication by a constant with a precomputed quotient
+// factor: w' = floor(w 2^290 / r), q = floor(y w' / 2^290), then
+// y w - q r lies in [0, 2r)). Here q comes from the columns 8..18 of the
+// 29-bit-limb product y w' only (the dropped columns add less than 2^265,
+// so the estimate is q or q - 1), and y w - q r is formed modulo 2^261 from
+// the low columns of y w and q r (it is below 3r < 2^261): 64 + 45 + 45
+// multiply-adds, no reduction of y beforehand and none afterwards. The
+// result is below 3r, enough for a consumer that reads only 32 bytes of a
+// value below 2^256. The work is cut into kSteps steps (see step()).
+struct ShoupMul {
+  static constexpr int kSteps = 12;
+  uint32_t a[10];  // y as ten 29-bit limbs
+  uint64_t h[11];  // columns 8..18 of y w'
+  uint32_t q[9];   // the quotient estimate mod 2^261, nine limbs
+  int64_t lo[9];   // columns 0..8 of y w - q r
+  fr_t out;
+
+  // rows i in [I0, I1) of the high columns
+  template <int I0, int I1>
+  __device__ FRNTT_INLINE void hi_rows(const uint32_t* wp) {
+#pragma unroll
+    for (int i = I0; i < I1; ++i)
+#pragma unroll
+      for (int j = (8 - i > 0 ? 8 - i : 0); j < 10; ++j) {
+        const int c = i + j - 8;
+        const uint64_t p = (uint64_t)a[i] * wp[j];
+        // first product of column c comes from row max(0, c - 1)
+        if (i == (c - 1 > 0 ? c - 1 : 0)) h[c] = p;
+        else h[c] += p;
+      }
+  }
+  // rows i in [I0, I1) of the low columns: + a_i w_j - q_i r_j
+  template <int I0, int I1>
+  __device__ FRNTT_INLINE void lo_rows(const uint32_t* w) {
+#pragma unroll
+    for (int i = I0; i < I1; ++i)
+#pragma unroll
+      for (int j = 0; i + j < 9; ++j) {
+        const int c = i + j;
+        const uint64_t p = (uint64_t)a[i] * w[j];
+        int64_t acc = i == 0 ? (int64_t)p : lo[c] + (int64_t)p;
+        acc += (int64_t)(int32_t)q[i] * (int64_t)(-(int32_t)fr_limb29(j));
+        lo[c] = acc;
+      }
+  }
+  // step Q of kSteps; wp, w: the Shoup operand form of the constant; y: nine
+  // words of the input (y < 2^290)
+  template <int Q>
+  __device__ FRNTT_INLINE void step(const uint32_t* wp, const uint32_t* w, const uint32_t* y) {
+    if constexpr (Q == 0) {
+#pragma unroll
+      for (int k = 0; k < 10; ++k) {
+        const int bit = 29 * k, wi = bit >> 5, sh = bit & 31;
+        uint32_t v;
+        if (sh + 29 <= 32 || wi + 1 >= 9) v = y[wi] >> sh;
+        else v = __builtin_amdgcn_alignbit(y[wi + 1], y[wi], (uint32_t)sh);
+        a[k] = v & kLimbMask;
+      }
+    } else if constexpr (Q == 1) {
+      hi_rows<0, 4>(wp);
+    } else if constexpr (Q == 2) {
+      hi_rows<4, 6>(wp);
+    } else if constexpr (Q == 3) {
+      hi_rows<6, 8>(wp);
+    } else if constexpr (Q == 4) {
+      hi_rows<8, 9>(wp);
+    } else if constexpr (Q == 5) {
+      hi_rows<9, 10>(wp);
+    } else if constexpr (Q == 6) {
+      // q = floor(sum_(c >= 8) h_c 2^(29 c) / 2^290): carry through columns
+      // 8 and 9, then columns 10..18 give the limbs of q
+      uint64_t c = h[0] >> 29;
+      c = (h[1] + c) >> 29;
+#pragma unroll
+      for (int m = 0; m < 9; ++m) {
+        const uint64_t v = h[2 + m] + c;
+        q[m] = (uint32_t)v & kLimbMask;
+        c = v >> 29;
+      }
+    } else if constexpr (Q == 7) {
+      lo_rows<0, 1>(w);
+    } else if constexpr (Q == 8) {
+      lo_rows<1, 3>(w);
+    } else if constexpr (Q == 9) {
+      lo_rows<3, 6>(w);
+    } else if constexpr (Q == 10) {
+      lo_rows<6, 9>(w);
+    } else {
+      // signed carries give the nine limbs of y w - q r mod 2^261 (the value
+      // itself: it lies in [0, 3r)); then eight 32-bit words
+      uint32_t l[9];
+      int64_t c = 0;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        const int64_t v = lo[k] + c;
+        l[k] = (uint32_t)v & kLimbMask;
+        c = v >> 29;
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int bit = 32 * i, k = bit / 29, sh = bit % 29;
+        uint32_t v = l[k] >> sh;
+        const int have = 29 - sh;
+        if (k + 1 < 9) v |= l[k + 1] << have;
+        if (have + 29 < 32 && k + 2 < 9) v |= l[k + 2] << (have + 29);
+        out.w[i] = v;
+      }
+    }
   }
 };
 

@@ -28,7 +28,8 @@ struct DevTables {
   const u32x4* tw_lo[2];      // [dir] mont w28^(+-j), j < 2^14            (w28 = w_{2^28})
   const u32x4* tw_hi[2];      // [dir] mont w28^(+-(2^14 j)), j < 2^14
   const u32x4* w4096[2];      // [dir] mont w_4096^(+-j), j < 4096
-  const u32x4* w4096_l[2];    // [dir] the same as nine 29-bit limbs (3 x 16 B per entry)
+  const u32x4* w4096_s[2];    // [dir] w_4096^(+-j) (not Montgomery) in the Shoup operand form:
+                              // 10 limbs of floor(w 2^290 / r), 9 limbs of w (5 x 16 B per entry)
   const u32x4* g_lo[2];       // [0] mont g^j, [1] mont g^-j, j < 2^14 (g = 5)
   const u32x4* g_hi[2];       // [0] mont g^(2^14 j), [1] g^-(2^14 j)
   const u32x4* ninv;          // mont 2^-L for L = 0..28
@@ -132,14 +133,20 @@ __device__ FRNTT_INLINE fr_t small_tw(const DevTables& T, int dir, int log_r, ui
   return ld_elem(T.w4096[dir], idx);
 }
 
-// The same twiddle as the nine 29-bit limbs of the Montgomery product.
-__device__ FRNTT_INLINE void small_tw_limbs(const DevTables& T, int dir, int log_r, uint32_t e, uint32_t* l) {
+// The same twiddle w_R^e (plain, not Montgomery) in the operand form of the
+// Shoup product: wp = the ten 29-bit limbs of floor(w 2^290 / r), w = the
+// nine limbs of w.
+__device__ FRNTT_INLINE void small_tw_shoup(const DevTables& T, int dir, int log_r, uint32_t e, uint32_t* wp,
+                                            uint32_t* w) {
   const uint32_t idx = (e & ((1u << log_r) - 1)) << (12 - log_r);
-  const u32x4* p = T.w4096_l[dir] + 3 * idx;
-  const u32x4 a = p[0], b = p[1], c = p[2];
-  l[0] = a.x; l[1] = a.y; l[2] = a.z; l[3] = a.w;
-  l[4] = b.x; l[5] = b.y; l[6] = b.z; l[7] = b.w;
-  l[8] = c.x;
+  const u32x4* p = T.w4096_s[dir] + 5 * idx;
+  const u32x4 a = p[0], b = p[1], c = p[2], d = p[3], f = p[4];
+  wp[0] = a.x; wp[1] = a.y; wp[2] = a.z; wp[3] = a.w;
+  wp[4] = b.x; wp[5] = b.y; wp[6] = b.z; wp[7] = b.w;
+  wp[8] = c.x; wp[9] = c.y;
+  w[0] = c.z; w[1] = c.w;
+  w[2] = d.x; w[3] = d.y; w[4] = d.z; w[5] = d.w;
+  w[6] = f.x; w[7] = f.y; w[8] = f.z;
 }
 
 // Montgomery form of g^(+-i) (i < 2^28).

@@ -430,7 +430,9 @@ constexpr int bat_lds_size() { return (1 << M) * 72; }  // i32x4 units
 //   KIND 0: nothing (last level of a forward or coset transform: the store
 //           reduces y < 3r),
 //   KIND 1: the inter-level twiddle w^(nn k) of the size-2^(m + q_log)
-//           sub-problem (one Montgomery product, output left below 2r),
+//           sub-problem: one Shoup product of the merged value, taken before
+//           the merge's own reduction (it accepts inputs below 2^290), output
+//           left below 3r,
 //   KIND 2: the pass twiddle w^(rest k) of the size-2^(l + S) sub-problem
 //           (last level of a non-last pass; the twiddle is the product of two
 //           table entries: two Montgomery products, output left below 2r),
@@ -445,12 +447,16 @@ constexpr int bat_lds_size() { return (1 << M) * 72; }  // i32x4 units
 template <int KIND>
 struct PairWork {
   static constexpr int kProducts = KIND == 0 ? 0 : (KIND == 2 || KIND == 6) ? 2 : KIND == 4 ? 3 : 1;
-  static constexpr int kSteps = kMergeSteps + 11 * kProducts;
+  // KIND 1: the merge without its last two (reduction) steps, then the Shoup
+  // product
+  static constexpr int kMergeUsed = KIND == 1 ? kMergeSteps - 2 : kMergeSteps;
+  static constexpr int kSteps = KIND == 1 ? kMergeUsed + ShoupMul::kSteps : kMergeSteps + 11 * kProducts;
   Merge mg;
   MontMul mm;
+  ShoupMul sh;
   fr_t tw, tw2, tw3;  // factors (Montgomery form), loaded when the pair starts
-  uint32_t twl[9];    // KIND 1: the inter-level twiddle as 29-bit limbs
-  fr_t y;             // the output of the pair: below 3r for KIND 0, canonical otherwise
+  uint32_t twp[10], tww[9];  // KIND 1: the inter-level twiddle in the Shoup operand form
+  fr_t y;             // the output of the pair: below 3r for KIND 0 and 1, canonical otherwise
 
   // step Q of a Montgomery product a * b -> out (11 steps); a LAZY product
   // leaves its output below 2r (the inter-level twiddle: the next level reads
@@ -465,12 +471,16 @@ struct PairWork {
   template <int S>
   __device__ FRNTT_INLINE void step() {
     constexpr int P0 = kMergeSteps, P1 = kMergeSteps + 11, P2 = kMergeSteps + 22;
-    if constexpr (S < P0) {
+    if constexpr (KIND == 1) {
+      if constexpr (S < kMergeUsed) {
+        mg.template step<S>();
+      } else {
+        sh.template step<S - kMergeUsed>(twp, tww, mg.y);
+        if constexpr (S == kSteps - 1) y = sh.out;
+      }
+    } else if constexpr (S < P0) {
       mg.template step<S>();
       if constexpr (S == P0 - 1) y = mg.result();
-    } else if constexpr (KIND == 1) {
-      if constexpr (S == P0) mm.load(twl, y);
-      else prod<S - P0, true>(tw, y, y);
     } else if constexpr (KIND == 5) {
       prod<S - P0, true>(tw, y, y);
     } else if constexpr (KIND == 3 || KIND == 7) {
@@ -575,7 +585,7 @@ struct TileLoop {
         const int k = kp + half * NKP;  // this lane's output digit: pair kp holds kp and kp + RHO/2
         wk.mg.a0 = n0;
         wk.mg.a1 = n1;
-        if (KIND == 1) small_tw_limbs(Tb, P.dir, g.m + g.q_log, (uint32_t)(nn * k), wk.twl);
+        if (KIND == 1) small_tw_shoup(Tb, P.dir, g.m + g.q_log, (uint32_t)(nn * k), wk.twp, wk.tww);
         if (KIND == 2) {
           const uint64_t e = (uint64_t)rest * (uint64_t)(kk + (k << g.pprev_log));
           const uint32_t E = (uint32_t)((e << (kMasterLog - P.log_r - P.log_s)) & ((1u << kMasterLog) - 1));

@@ -4,9 +4,9 @@
 //   caption) and notes that tables growing with N run out of memory (3-step
 //   NTT, Introduction); here the pass twiddles w_M^e for any M <= 2^28 come
 //   from two 2^14-entry tables of w_{2^28} powers and one extra product;
-//   in-pass twiddles come from one 4096-entry table, kept a second time as
-//   nine 29-bit limbs per entry (the operand form of the Montgomery product)
-//   for the matrix form's inter-level twiddles.
+//   in-pass twiddles come from one 4096-entry table, kept a second time for
+//   the matrix form's inter-level twiddles in the operand form of its Shoup
+//   product: w as nine 29-bit limbs and w' = floor(w 2^290 / r) as ten.
 // * byte-limb constant blocks for the matrix form (Alg. 1, Precomputation:
 //   the BAT-shifted constants I_{i,b} = ... << 8b mod Q and their byte split
 //   E[i,b,j,h]): for a radix rho, block j holds the signed base-256 digits
@@ -30,20 +30,89 @@ void put_elem(uint8_t* dst, const Fe& a) { std::memcpy(dst, a.v, 32); }
 
 uint8_t byte_of(const Fe& a, int h) { return (uint8_t)(a.v[h >> 3] >> (8 * (h & 7))); }
 
-// nine 29-bit limbs of a canonical value (limb k = bits [29k, 29k + 29)),
-// then three zero words: 48 bytes
-void put_limbs29(uint8_t* dst, const Fe& a) {
-  uint32_t l[12] = {};
-  for (int k = 0; k < 9; ++k) {
+// 29-bit limbs of a little-endian word array (limb k = bits [29k, 29k + 29))
+void limbs29(const uint32_t* w, int nwords, uint32_t* l, int nlimbs) {
+  for (int k = 0; k < nlimbs; ++k) {
     uint32_t v = 0;
     for (int b = 0; b < 29; ++b) {
       const int bit = 29 * k + b;
-      if (bit < 256 && ((a.v[bit >> 6] >> (bit & 63)) & 1)) v |= 1u << b;
+      if (bit < 32 * nwords && ((w[bit >> 5] >> (bit & 31)) & 1)) v |= 1u << b;
     }
     l[k] = v;
   }
-  std::memcpy(dst, l, 48);
 }
+
+// x * y mod 2^(32 n) on n-word little-endian integers
+void mul_lo(const uint32_t* x, const uint32_t* y, uint32_t* out, int n) {
+  std::vector<uint32_t> o(n, 0);
+  for (int i = 0; i < n; ++i) {
+    uint64_t c = 0;
+    for (int j = 0; i + j < n; ++j) {
+      const uint64_t t = (uint64_t)x[i] * y[j] + o[i + j] + c;
+      o[i + j] = (uint32_t)t;
+      c = t >> 32;
+    }
+  }
+  for (int i = 0; i < n; ++i) out[i] = o[i];
+}
+
+constexpr int kShoupK = 290;   // w' = floor(w 2^290 / r): products of inputs below 2^290
+constexpr int kDivWords = 10;  // w' < 2^290 < 2^320
+
+// The Shoup operand form of a canonical w: words 0..9 the ten 29-bit limbs of
+// w' = floor(w 2^290 / r), words 10..18 the nine limbs of w, word 19 zero.
+// w 2^290 - (w 2^290 mod r) is a multiple of r, and w' below 2^320, so w' is
+// that difference times r^-1 mod 2^320 (exact division by an odd divisor).
+struct ShoupForm {
+  Field F;
+  Fe two_k;                     // 2^290 mod r
+  uint32_t rinv[kDivWords];     // r^-1 mod 2^320
+  ShoupForm() {
+    two_k = host::from_u64(1);
+    for (int i = 0; i < kShoupK; ++i) two_k = host::add(two_k, two_k);
+    uint32_t r[kDivWords] = {};
+    for (int i = 0; i < 8; ++i) r[i] = fr_mod_word(i);
+    // Newton iteration x <- x (2 - r x) doubles the correct low bits: 1 -> 512
+    uint32_t x[kDivWords] = {1};
+    for (int it = 0; it < 9; ++it) {
+      uint32_t rx[kDivWords], two_minus[kDivWords], nx[kDivWords];
+      mul_lo(r, x, rx, kDivWords);
+      uint64_t br = 0;
+      for (int i = 0; i < kDivWords; ++i) {  // 2 - r x mod 2^320
+        const uint64_t d = (uint64_t)(i == 0 ? 2u : 0u) - rx[i] - br;
+        two_minus[i] = (uint32_t)d;
+        br = (d >> 32) & 1;
+      }
+      mul_lo(x, two_minus, nx, kDivWords);
+      std::memcpy(x, nx, sizeof x);
+    }
+    std::memcpy(rinv, x, sizeof rinv);
+  }
+  void put(uint8_t* dst, const Fe& w) const {
+    const Fe rem = F.mul(w, two_k);  // w 2^290 mod r
+    // D = w 2^290 - rem, low 320 bits (w 2^290 has zero low 290 bits)
+    uint32_t D[kDivWords] = {};
+    for (int bit = 0; bit < 320; ++bit) {
+      const int src = bit - kShoupK;
+      if (src >= 0 && src < 256 && ((w.v[src >> 6] >> (src & 63)) & 1)) D[bit >> 5] |= 1u << (bit & 31);
+    }
+    uint64_t br = 0;
+    for (int i = 0; i < kDivWords; ++i) {
+      const uint32_t rw = i < 8 ? (uint32_t)(rem.v[i >> 1] >> (32 * (i & 1))) : 0u;
+      const uint64_t d = (uint64_t)D[i] - rw - br;
+      D[i] = (uint32_t)d;
+      br = (d >> 32) & 1;
+    }
+    uint32_t wp[kDivWords];
+    mul_lo(D, rinv, wp, kDivWords);
+    uint32_t words[20] = {};
+    limbs29(wp, kDivWords, words, 10);
+    uint32_t ww[8];
+    for (int i = 0; i < 8; ++i) ww[i] = (uint32_t)(w.v[i >> 1] >> (32 * (i & 1)));
+    limbs29(ww, 8, words + 10, 9);
+    std::memcpy(dst, words, 80);
+  }
+};
 
 // Signed base-256 digits of a canonical value: sum_h e_h 256^h = a, e_h in [-128, 127].
 void signed_digits(const Fe& a, int8_t e[32]) {
@@ -62,7 +131,7 @@ void signed_digits(const Fe& a, int8_t e[32]) {
 }
 
 struct Layout {
-  size_t tw_lo[2], tw_hi[2], w4096[2], w4096_l[2], g_lo[2], g_hi[2], ninv;
+  size_t tw_lo[2], tw_hi[2], w4096[2], w4096_s[2], g_lo[2], g_hi[2], ninv;
   size_t bat[2][6], bat_init[2][6];
   size_t total;
 };
@@ -79,7 +148,7 @@ Layout make_layout() {
     L.tw_lo[d] = take((size_t)32 << kSplit);
     L.tw_hi[d] = take((size_t)32 << kSplit);
     L.w4096[d] = take(32 * 4096);
-    L.w4096_l[d] = take(48 * 4096);
+    L.w4096_s[d] = take(80 * 4096);
     L.g_lo[d] = take((size_t)32 << kSplit);
     L.g_hi[d] = take((size_t)32 << kSplit);
   }
@@ -103,6 +172,7 @@ static void fill_tables(uint8_t* h, const Layout& L) {
   Fe dev_r = one;
   for (int i = 0; i < 261; ++i) dev_r = host::add(dev_r, dev_r);
   auto dev_m = [&](const Fe& x) { return F.mul(x, dev_r); };
+  const ShoupForm shoup;
   Fe w28[2];
   w28[0] = F.root(kMasterLog);
   w28[1] = F.inv(w28[0]);
@@ -122,7 +192,7 @@ static void fill_tables(uint8_t* h, const Layout& L) {
     p = one;
     for (int j = 0; j < 4096; ++j) {
       put_elem(h + L.w4096[d] + 32 * (size_t)j, dev_m(p));
-      put_limbs29(h + L.w4096_l[d] + 48 * (size_t)j, dev_m(p));
+      shoup.put(h + L.w4096_s[d] + 80 * (size_t)j, p);
       p = F.mul(p, w4096);
     }
     // g^(+-j) and g^(+-(2^14 j))
@@ -227,7 +297,7 @@ int build_tables(frntt_ctx* ctx) {
     T.tw_lo[d] = (const u32x4*)(b + L.tw_lo[d]);
     T.tw_hi[d] = (const u32x4*)(b + L.tw_hi[d]);
     T.w4096[d] = (const u32x4*)(b + L.w4096[d]);
-    T.w4096_l[d] = (const u32x4*)(b + L.w4096_l[d]);
+    T.w4096_s[d] = (const u32x4*)(b + L.w4096_s[d]);
     T.g_lo[d] = (const u32x4*)(b + L.g_lo[d]);
     T.g_hi[d] = (const u32x4*)(b + L.g_hi[d]);
     T.bat[d][0] = nullptr;
