@@ -54,6 +54,7 @@ extern "C" {
 
 typedef struct frntt_ctx frntt_ctx;
 typedef struct frntt_server frntt_server;
+typedef struct frntt_rns_field frntt_rns_field;
 
 /* Status codes returned by every call. */
 enum {
@@ -257,6 +258,32 @@ int frntt_rns_decode(frntt_ctx *ctx, const void *xp, void *out, int64_t n, void 
  * paper's arithmetic ablation: out = a b 2^-261 mod r for canonical a, b
  * (nine 29-bit limbs). */
 int frntt_mont_mul(frntt_ctx *ctx, const void *a, const void *b, void *out, int64_t n, void *stream);
+
+/* ---- the same product over other prime fields (the paper's 256/377/753-bit
+ * precisions; Arithmetic Optimizations and the Ablation Study) ----
+ * A field object holds the tables of one odd prime modulus M given as m_words
+ * little-endian 32-bit words: 8 words for M below 2^254, 12 for M below
+ * 2^377, 24 for M below 2^753 (and M above 2^32). The shape follows the width:
+ *   M words | base Q (I residues, words/element) | base P (J, words) | Montgomery limbs
+ *      8    |            17, 20                  |      9, 12        |  9
+ *     12    |            25, 28                  |     13, 16        | 13
+ *     24    |            49, 52                  |     25, 28        | 26
+ * with the moduli q_i, p_j the first I + J primes below 2^31 - 2^24 and
+ * |W'| < (4 I 255 + 1) M. Canonical elements take m_words words. Creation is
+ * synchronous (tables are built on the host and copied); the calls below are
+ * enqueued on `stream`; destroy waits for the device. Errors: EINVAL (null
+ * pointer, n < 0, m_words not 8/12/24), ERANGE (M even, below 2^32 or too
+ * wide for m_words), EALIGN (pointers not 16-byte aligned), ENOMEM, EHIP.
+ * With M = r (8 words) the results equal those of the calls above. */
+int frntt_rns_field_create(frntt_rns_field **out, frntt_ctx *ctx, const uint32_t *m, int m_words);
+int frntt_rns_field_destroy(frntt_rns_field *f);
+/* I, J and the words per element of base Q and base P. */
+int frntt_rns_field_shape(const frntt_rns_field *f, int *n_q, int *n_p, int *q_words, int *p_words);
+int frntt_rns_field_encode(frntt_rns_field *f, const void *a, void *xq, int64_t n, void *stream);
+int frntt_rns_field_mul(frntt_rns_field *f, const void *xa, const void *xb, void *xp, int64_t n, void *stream);
+int frntt_rns_field_decode(frntt_rns_field *f, const void *xp, void *out, int64_t n, void *stream);
+/* out = a b 2^(-29 L) mod M (L = 9, 13, 26 limbs for 8, 12, 24 words). */
+int frntt_rns_field_mont_mul(frntt_rns_field *f, const void *a, const void *b, void *out, int64_t n, void *stream);
 
 /* Last hipError_t seen by the context (0 if none). */
 int frntt_last_hip_error(const frntt_ctx *ctx);

@@ -10,16 +10,19 @@ TEST INFRASTRUCTURE ONLY. Nothing in the product path imports this module;
 only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may use it. It shares no code with the HIP library.
 
-Parameters (the paper leaves them open; these are this implementation's):
-  M   = r, the BN254 scalar-field prime;
-  Q   = product of I = 17 primes q_i, the largest below 2^31 - 2^24, so that
-        Q > 2 M^2 (a product of two canonical values never wraps Q);
-  P   = product of J = 9 primes p_j, the next ones below the q_i, so that
-        P exceeds twice any lazily reduced output;
+Parameters (the paper leaves them open; these are this implementation's),
+for the three field widths the paper evaluates (256/377/753 bits):
+  M   = r, the BN254 scalar-field prime (254 bits), or the largest prime
+        below 2^377 or 2^753 (the paper names no curves for those widths);
+  Q   = product of I primes q_i (I = 17, 25, 49), the largest below
+        2^31 - 2^24, so that Q > 2 M^2 (a product of two canonical values
+        never wraps Q);
+  P   = product of J primes p_j (J = 9, 13, 25), the next ones below the
+        q_i, so that P exceeds twice any lazily reduced output;
   w   = 32: residues are kept in Montgomery form x z mod q (z = 2^w),
         y = z^-1 (mod Q for the Q side, mod P for the P side);
-  B   = H = 4 bytes per residue; u = 15 fraction bits for the overflow
-        count k.
+  B   = H = 4 bytes per residue; u = 15, 16, 17 fraction bits for the
+        overflow count k of Main (15, 16, 16 for the decode).
 Readings of the printed algorithm:
   * I_i uses ((Q/q_i)^-1 mod q_i), the CRT coefficient of residue i (the
     text prints "mod p_i");
@@ -66,15 +69,55 @@ def _is_prime(n: int) -> bool:
     return True
 
 
-def moduli() -> tuple[list[int], list[int]]:
-    """q_0 > q_1 > ... > q_16 > p_0 > ... > p_8: consecutive primes below 2^31 - 2^24."""
+def moduli(n_q: int = I_RES, n_p: int = J_RES) -> tuple[list[int], list[int]]:
+    """q_0 > ... > q_(n_q-1) > p_0 > ... > p_(n_p-1): consecutive primes below 2^31 - 2^24."""
     out = []
     n = MOD_BOUND - 1
-    while len(out) < I_RES + J_RES:
+    while len(out) < n_q + n_p:
         if _is_prime(n):
             out.append(n)
         n -= 2 if n % 2 else 1
-    return out[:I_RES], out[I_RES:]
+    return out[:n_q], out[n_q:]
+
+
+def _prev_prime(n: int) -> int:
+    """Largest probable prime below n (Miller-Rabin with the 40 bases
+    2..41; a one-off parameter choice, pinned against sympy in the tests)."""
+    def probable_prime(x):
+        if x % 2 == 0:
+            return x == 2
+        d, s = x - 1, 0
+        while d % 2 == 0:
+            d //= 2
+            s += 1
+        for a in range(2, 42):
+            y = pow(a, d, x)
+            if y in (1, x - 1):
+                continue
+            for _ in range(s - 1):
+                y = y * y % x
+                if y == x - 1:
+                    break
+            else:
+                return False
+        return True
+    x = n - 1
+    while not probable_prime(x):
+        x -= 1
+    return x
+
+
+# field width -> (modulus, I, J, u of Main, u of the decode)
+WIDTHS = {254: (R_MOD, 17, 9, 15, 15)}
+
+
+def width_params(bits: int):
+    """(M, I, J, u_mul, u_dec) of a field width (254: BN254 r; 377, 753: the
+    largest prime below 2^bits)."""
+    if bits not in WIDTHS:
+        u = {377: (25, 13, 16, 16), 753: (49, 25, 17, 16)}[bits]
+        WIDTHS[bits] = (_prev_prime(1 << bits),) + u
+    return WIDTHS[bits]
 
 
 def _prod(xs):
@@ -204,17 +247,20 @@ def decode(xp: np.ndarray, base: list[int], m: int = R_MOD, w: int = W_BITS) -> 
     return out
 
 
-def modmul(a: list[int], b: list[int]) -> list[int]:
-    """a b mod r through encode, residue-wise product, Alg. 1 Main and decode."""
-    qs, ps = moduli()
-    pre = Precomputation(qs, ps)
+def modmul(a: list[int], b: list[int], bits: int = 254) -> list[int]:
+    """a b mod M through encode, residue-wise product, Alg. 1 Main and decode."""
+    m, n_q, n_p, u, _ = width_params(bits)
+    qs, ps = moduli(n_q, n_p)
+    pre = Precomputation(qs, ps, m=m, u=u)
     x = vec_mul(encode(a, qs), encode(b, qs), qs)
-    return decode(main(pre, x), ps)
+    return decode(main(pre, x), ps, m=m)
 
 
 def mont_product(a: list[int], b: list[int], m: int = R_MOD) -> list[int]:
-    """The radix Montgomery product the VALU baseline computes: a b 2^-261 mod r."""
-    rinv = pow(1 << 261, -1, m)
+    """The radix Montgomery product the VALU baseline computes: a b 2^(-29 L)
+    mod m with L = ceil(bits(m) / 29) 29-bit limbs (2^-261 for BN254 r)."""
+    limbs = -(-m.bit_length() // 29)
+    rinv = pow(1 << (29 * limbs), -1, m)
     return [x * y % m * rinv % m for x, y in zip(a, b)]
 
 

@@ -5,9 +5,9 @@ declared in include/frntt.h). This package only marshals arguments to it;
 see ``paper_2604_17808_amd.frntt``.
 """
 from .frntt import (FWD, INV, COSET, COSET_INV, ALGO_AUTO, ALGO_BUTTERFLY, ALGO_FOURSTEP_MFMA,
-                    FrnttError, Context, Server, lib, library_path, rns_moduli, RNS_Q_WORDS,
-                    RNS_P_WORDS)
+                    FrnttError, Context, Server, RnsField, lib, library_path, rns_moduli, RNS_Q_WORDS,
+                    RNS_P_WORDS, FIELD_377, FIELD_753)
 
 __all__ = ["FWD", "INV", "COSET", "COSET_INV", "ALGO_AUTO", "ALGO_BUTTERFLY",
            "ALGO_FOURSTEP_MFMA", "FrnttError", "Context", "Server", "lib", "library_path",
-           "rns_moduli", "RNS_Q_WORDS", "RNS_P_WORDS"]
+           "rns_moduli", "RNS_Q_WORDS", "RNS_P_WORDS", "RnsField", "FIELD_377", "FIELD_753"]

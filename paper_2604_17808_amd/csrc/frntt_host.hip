@@ -549,7 +549,7 @@ int frntt_ctx_destroy(frntt_ctx* ctx) {
     }
     if (ctx->valid_flag) hipFree(ctx->valid_flag);
     if (ctx->table_mem) hipFree(ctx->table_mem);
-    if (ctx->rns_mem) hipFree(ctx->rns_mem);
+    destroy_rns_field(ctx->rns_default);
     for (auto& kv : ctx->pass_tw) hipFree(kv.second);
   }
   delete ctx;

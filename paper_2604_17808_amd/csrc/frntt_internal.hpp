@@ -89,8 +89,7 @@ struct frntt_ctx {
   frntt::DevTables tables{};
   unsigned int* valid_flag = nullptr;  // device flag for FRNTT_VALIDATE
   void* noalloc_scratch = nullptr;     // this device's static scratch of ntt_transform_noalloc
-  void* rns_mem = nullptr;             // operand tables of the RNS lazy product
-  frntt::RnsTables rns{};
+  frntt_rns_field* rns_default = nullptr;  // RNS lazy product over Fr (BN254), built at creation
   // plan overrides [algo][log_n]
   frntt::Plan plan_override[3][29];
   bool has_override[3][29] = {};
@@ -108,8 +107,11 @@ struct frntt_ctx {
 namespace frntt {
 
 int set_hip_error(const frntt_ctx* ctx, hipError_t e);
-// Operand tables of the RNS lazy product (built at context creation).
+// The context's RNS lazy product over Fr (built at context creation), any
+// other field's tables, and their release.
 int build_rns_tables(frntt_ctx* ctx);
+int create_rns_field(frntt_ctx* ctx, const uint32_t* m, int mw, frntt_rns_field** out);
+void destroy_rns_field(frntt_rns_field* f);
 // Default or overridden plan for (algo, log_n); algo must be BUTTERFLY or MFMA.
 // Takes ctx->mu.
 Plan plan_for(const frntt_ctx* ctx, int algo, int log_n);

@@ -77,10 +77,23 @@ SIGNATURES = {
     "frntt_rns_mul": (_i, [_vp, _vp, _vp, _vp, ctypes.c_int64, _vp]),
     "frntt_rns_decode": (_i, [_vp, _vp, _vp, ctypes.c_int64, _vp]),
     "frntt_mont_mul": (_i, [_vp, _vp, _vp, _vp, ctypes.c_int64, _vp]),
+    "frntt_rns_field_create": (_i, [ctypes.POINTER(_vp), _vp, ctypes.POINTER(ctypes.c_uint32), _i]),
+    "frntt_rns_field_destroy": (_i, [_vp]),
+    "frntt_rns_field_shape": (_i, [_vp, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i),
+                                   ctypes.POINTER(_i)]),
+    "frntt_rns_field_encode": (_i, [_vp, _vp, _vp, ctypes.c_int64, _vp]),
+    "frntt_rns_field_mul": (_i, [_vp, _vp, _vp, _vp, ctypes.c_int64, _vp]),
+    "frntt_rns_field_decode": (_i, [_vp, _vp, _vp, ctypes.c_int64, _vp]),
+    "frntt_rns_field_mont_mul": (_i, [_vp, _vp, _vp, _vp, ctypes.c_int64, _vp]),
 }
 
 RNS_Q_WORDS = 20
 RNS_P_WORDS = 12
+
+# The wider moduli of the RNS lazy product: the largest primes below 2^377 and
+# 2^753 (the paper evaluates 256/377/753-bit fields without naming curves).
+FIELD_377 = (1 << 377) - 259
+FIELD_753 = (1 << 753) - 1101
 
 _lib = None
 
@@ -254,6 +267,48 @@ class Context:
 
     def last_hip_error(self) -> int:
         return lib().frntt_last_hip_error(self._h)
+
+
+class RnsField:
+    """RNS lazy modular product over the prime field of `modulus` (at most 254,
+    377 or 753 bits: 8, 12 or 24 words); see frntt_rns_field_* in
+    include/frntt.h. Pointers are device addresses of n elements."""
+
+    def __init__(self, ctx: "Context", modulus: int):
+        bits = modulus.bit_length()
+        self.words = 8 if bits <= 254 else 12 if bits <= 377 else 24
+        self.modulus = modulus
+        m = (ctypes.c_uint32 * self.words)(*[(modulus >> (32 * w)) & 0xFFFFFFFF for w in range(self.words)])
+        h = _vp()
+        _check(lib().frntt_rns_field_create(ctypes.byref(h), ctx.handle, m, self.words), "frntt_rns_field_create")
+        self._h = h
+        q, p, qw, pw = _i(), _i(), _i(), _i()
+        _check(lib().frntt_rns_field_shape(self._h, ctypes.byref(q), ctypes.byref(p), ctypes.byref(qw),
+                                           ctypes.byref(pw)), "frntt_rns_field_shape")
+        self.n_q, self.n_p, self.q_words, self.p_words = q.value, p.value, qw.value, pw.value
+
+    def encode(self, a: int, xq: int, n: int, stream: int = 0):
+        return _check(lib().frntt_rns_field_encode(self._h, a, xq, n, stream), "frntt_rns_field_encode")
+
+    def mul(self, xa: int, xb: int, xp: int, n: int, stream: int = 0):
+        return _check(lib().frntt_rns_field_mul(self._h, xa, xb, xp, n, stream), "frntt_rns_field_mul")
+
+    def decode(self, xp: int, out: int, n: int, stream: int = 0):
+        return _check(lib().frntt_rns_field_decode(self._h, xp, out, n, stream), "frntt_rns_field_decode")
+
+    def mont_mul(self, a: int, b: int, out: int, n: int, stream: int = 0):
+        return _check(lib().frntt_rns_field_mont_mul(self._h, a, b, out, n, stream), "frntt_rns_field_mont_mul")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().frntt_rns_field_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:

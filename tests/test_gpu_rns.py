@@ -191,3 +191,146 @@ def test_rns_errors(ctx):
     assert L.frntt_rns_encode(ctx.handle, p + 4, p, 1, None) == fr.frntt.EALIGN
     assert L.frntt_rns_decode(ctx.handle, p, p + 8, 1, None) == fr.frntt.EALIGN
     assert L.frntt_mont_mul(ctx.handle, p, None, p, 1, None) == fr.frntt.EINVAL
+
+
+# ---- the field objects: BN254 r through the generic path, and 377/753 bits ---
+
+WIDTHS = [254, 377, 753]
+
+
+@pytest.fixture(scope="module")
+def fields(ctx):
+    out = {254: fr.RnsField(ctx, M), 377: fr.RnsField(ctx, fr.FIELD_377), 753: fr.RnsField(ctx, fr.FIELD_753)}
+    yield out
+    for f in out.values():
+        f.close()
+
+
+def ints_to_u32(vals, words) -> np.ndarray:
+    out = np.zeros((len(vals), words), dtype=np.uint32)
+    for i, v in enumerate(vals):
+        for w in range(words):
+            out[i, w] = (v >> (32 * w)) & 0xFFFFFFFF
+    return out
+
+
+def u32_to_ints(a: np.ndarray):
+    a = np.asarray(a, dtype=np.uint64)
+    return [sum(int(x) << (32 * w) for w, x in enumerate(row)) for row in a]
+
+
+def u32_dev(arr: np.ndarray):
+    return torch.from_numpy(np.ascontiguousarray(arr, dtype=np.uint32).view(np.int32).reshape(-1).copy()).to("cuda:0")
+
+
+def wide_operands(m, n, seed):
+    import random
+    rnd = random.Random(seed)
+    a = [rnd.randrange(m) for _ in range(n)]
+    b = [rnd.randrange(m) for _ in range(n)]
+    edges = [(0, 0), (1, m - 1), (m - 1, m - 1), (m - 1, 1)]
+    for i, (x, y) in enumerate(edges[:n]):
+        a[i], b[i] = x, y
+    return a, b
+
+
+@pytest.mark.parametrize("bits", WIDTHS)
+@pytest.mark.parametrize("n", [1, 33, 1000])
+def test_field_steps_match_oracle(fields, bits, n):
+    f = fields[bits]
+    m, n_q, n_p, u, _ = R.width_params(bits)
+    qs, ps = R.moduli(n_q, n_p)
+    pre = R.Precomputation(qs, ps, m=m, u=u)
+    _say(f"rns field {bits} bits n={n}")
+    a, b = wide_operands(m, n, 7 * bits + n)
+    s = torch.cuda.current_stream().cuda_stream
+    # encode
+    ta = u32_dev(ints_to_u32(a, f.words))
+    xq = torch.full((n * f.q_words,), -1, dtype=torch.int32, device="cuda:0")
+    f.encode(ta.data_ptr(), xq.data_ptr(), n, s)
+    torch.cuda.synchronize()
+    want = np.zeros((n, f.q_words), dtype=np.uint32)
+    ea = R.encode(a, qs)
+    want[:, :n_q] = ea.astype(np.uint32)
+    assert np.array_equal(host_u32(xq, f.q_words), want)
+    # product (Alg. 1 Main after the residue-wise product), from oracle inputs
+    eb = R.encode(b, qs)
+    wp = R.main(pre, R.vec_mul(ea, eb, qs))
+    xa, xb = residues_to_dev(ea, f.q_words), residues_to_dev(eb, f.q_words)
+    xp = torch.full((n * f.p_words,), -1, dtype=torch.int32, device="cuda:0")
+    f.mul(xa.data_ptr(), xb.data_ptr(), xp.data_ptr(), n, s)
+    torch.cuda.synchronize()
+    got = host_u32(xp, f.p_words)
+    assert np.array_equal(got[:, :n_p], wp.astype(np.uint32)) and not got[:, n_p:].any()
+    # decode, from oracle inputs
+    tx = residues_to_dev(wp, f.p_words)
+    out = torch.zeros((n * f.words,), dtype=torch.int32, device="cuda:0")
+    f.decode(tx.data_ptr(), out.data_ptr(), n, s)
+    torch.cuda.synchronize()
+    assert u32_to_ints(host_u32(out, f.words)) == R.decode(wp, ps, m=m) == [x * y % m for x, y in zip(a, b)]
+    # radix Montgomery baseline
+    tb = u32_dev(ints_to_u32(b, f.words))
+    f.mont_mul(ta.data_ptr(), tb.data_ptr(), out.data_ptr(), n, s)
+    torch.cuda.synchronize()
+    assert u32_to_ints(host_u32(out, f.words)) == R.mont_product(a, b, m)
+
+
+@pytest.mark.parametrize("bits", [377, 753])
+def test_field_pipeline_sampled(fields, bits):
+    f = fields[bits]
+    m = R.width_params(bits)[0]
+    n = 1 << 18
+    _say(f"rns field pipeline {bits} bits n={n}")
+    a, b = wide_operands(m, 2048, bits)
+    idx = np.arange(n) % 2048                      # repeat 2048 operands over the whole range
+    ta = u32_dev(ints_to_u32(a, f.words)[idx])
+    tb = u32_dev(ints_to_u32(b, f.words)[idx])
+    s = torch.cuda.current_stream().cuda_stream
+    xa = torch.empty((n * f.q_words,), dtype=torch.int32, device="cuda:0")
+    xb = torch.empty_like(xa)
+    xp = torch.empty((n * f.p_words,), dtype=torch.int32, device="cuda:0")
+    out = torch.empty((n * f.words,), dtype=torch.int32, device="cuda:0")
+    f.encode(ta.data_ptr(), xa.data_ptr(), n, s)
+    f.encode(tb.data_ptr(), xb.data_ptr(), n, s)
+    f.mul(xa.data_ptr(), xb.data_ptr(), xp.data_ptr(), n, s)
+    f.decode(xp.data_ptr(), out.data_ptr(), n, s)
+    torch.cuda.synchronize()
+    got = host_u32(out, f.words)
+    want = [x * y % m for x, y in zip(a, b)]
+    rng = np.random.default_rng(bits)
+    for i in np.concatenate([[0, 1, n - 1], rng.integers(0, n, 2000)]):
+        assert u32_to_ints(got[i:i + 1])[0] == want[i % 2048], i
+
+
+def test_bn254_field_object_equals_context_calls(ctx, fields):
+    f = fields[254]
+    n = 777
+    a, b = operands(n, 31)
+    ta, tb = dev(ints_to_words(a)), dev(ints_to_words(b))
+    s = torch.cuda.current_stream().cuda_stream
+    outs = []
+    for enc, mul, dec in ((ctx.rns_encode, ctx.rns_mul, ctx.rns_decode), (f.encode, f.mul, f.decode)):
+        xa = torch.empty((n * QW,), dtype=torch.int32, device="cuda:0")
+        xb = torch.empty_like(xa)
+        xp = torch.empty((n * PW,), dtype=torch.int32, device="cuda:0")
+        o = torch.empty((n * 4,), dtype=torch.int64, device="cuda:0")
+        enc(ta.data_ptr(), xa.data_ptr(), n, s)
+        enc(tb.data_ptr(), xb.data_ptr(), n, s)
+        mul(xa.data_ptr(), xb.data_ptr(), xp.data_ptr(), n, s)
+        dec(xp.data_ptr(), o.data_ptr(), n, s)
+        torch.cuda.synchronize()
+        outs.append((xa.cpu().numpy(), xp.cpu().numpy(), o.cpu().numpy()))
+    for x, y in zip(*outs):
+        assert np.array_equal(x, y)
+    assert (f.n_q, f.n_p, f.q_words, f.p_words) == (17, 9, QW, PW)
+
+
+def test_field_errors(ctx):
+    import ctypes
+    L = fr.lib()
+    h = ctypes.c_void_p()
+    even = (ctypes.c_uint32 * 8)(*([2] + [0] * 6 + [1]))
+    assert L.frntt_rns_field_create(ctypes.byref(h), ctx.handle, even, 8) == fr.frntt.ERANGE
+    wide = (ctypes.c_uint32 * 8)(*([1] + [0] * 6 + [0x80000000]))   # 256 bits: too wide for 8 words
+    assert L.frntt_rns_field_create(ctypes.byref(h), ctx.handle, wide, 8) == fr.frntt.ERANGE
+    assert L.frntt_rns_field_create(ctypes.byref(h), ctx.handle, even, 10) == fr.frntt.EINVAL

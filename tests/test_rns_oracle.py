@@ -150,3 +150,54 @@ def test_planted_missing_y_fails():
         pre.C = [[[(pre.z * (pre.Ib[i][b] % M)) % p for p in pre.dst] for b in range(4)] for i in range(len(pre.src))]
         pre.f = [[-((-pre.Ib[i][b] << pre.u) // Q) for b in range(4)] for i in range(len(pre.src))]
     assert not _modmul_with(no_y)
+
+
+# ---- wider fields (377 and 753 bits) ---------------------------------------
+
+@pytest.mark.parametrize("bits", [377, 753])
+def test_wide_parameters(bits):
+    m, n_q, n_p, u, u_dec = R.width_params(bits)
+    assert m == sympy.prevprime(1 << bits) and m.bit_length() == bits
+    qs, ps = R.moduli(n_q, n_p)
+    expect = [sympy.prevprime(R.MOD_BOUND)]
+    while len(expect) < n_q + n_p:
+        expect.append(sympy.prevprime(expect[-1]))
+    assert qs + ps == expect
+    Q, P = R._prod(qs), R._prod(ps)
+    assert Q > 2 * (m - 1) ** 2
+    assert P > 2 * (4 * n_q * 255 + 1) * m
+    # exact k: the estimate's error stays below 1 - (products / Q)
+    assert 4 * n_q * 255 / 2 ** u + (m - 1) ** 2 / Q < 1
+    # the decode's nearest-integer k: error below 1/2 with margin
+    assert 4 * n_p * 255 / 2 ** u_dec < 0.5
+
+
+@pytest.mark.parametrize("bits", [377, 753])
+def test_wide_modmul_is_the_field_product(bits):
+    m = R.width_params(bits)[0]
+    rnd = random.Random(bits)
+    a = [rnd.randrange(m) for _ in range(150)] + [0, 1, m - 1, m - 1]
+    b = [rnd.randrange(m) for _ in range(150)] + [m - 1, m - 1, m - 1, 1]
+    assert R.modmul(a, b, bits) == [x * y % m for x, y in zip(a, b)]
+
+
+@pytest.mark.parametrize("bits", [377, 753])
+def test_wide_overflow_count_exact(bits):
+    m, n_q, n_p, u, _ = R.width_params(bits)
+    qs, ps = R.moduli(n_q, n_p)
+    pre = R.Precomputation(qs, ps, m=m, u=u)
+    rnd = random.Random(bits + 1)
+    a = [rnd.randrange(m) for _ in range(60)] + [m - 1]
+    b = [rnd.randrange(m) for _ in range(60)] + [m - 1]
+    x = R.vec_mul(R.encode(a, qs), R.encode(b, qs), qs)
+    _, k = R.main(pre, x, return_k=True)
+    assert k.tolist() == R.main_exact_k(pre, x)
+
+
+def test_wide_mont_product_definition():
+    for bits in (377, 753):
+        m = R.width_params(bits)[0]
+        limbs = -(-bits // 29)
+        a, b = [3, m - 1, m // 2], [m - 2, m - 1, 5]
+        for o, x, y in zip(R.mont_product(a, b, m), a, b):
+            assert o * (1 << (29 * limbs)) % m == x * y % m
