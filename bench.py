@@ -326,6 +326,68 @@ def bench_f2(ctx, torch, fr, stream, steps):
     return out
 
 
+def bench_f3(ctx, torch, fr, stream, steps):
+    """The RNS lazy product against the radix Montgomery product at the wider
+    widths the paper evaluates (the largest primes below 2^377 and 2^753), at
+    2^20 and 2^22 elements: elements per second of each call and of the whole
+    pipeline, the HBM bandwidth of each call, the product's int8 MFMA rate.
+    Inputs are uniform below 2^bits (values of M or above, probability
+    about 2^-369, are not excluded)."""
+    out = {}
+    for bits, modulus in ((377, fr.FIELD_377), (753, fr.FIELD_753)):
+        f = fr.RnsField(ctx, modulus)
+        mw, qw, pw = f.words, f.q_words, f.p_words
+        # int8 operations of Main per element: row blocks x K steps of 32x32x32 per 32 elements
+        rbm, ksq = (4 * f.n_p + 3 + 31) // 32, (f.n_q + 7) // 8
+        ops = rbm * ksq * 2 * 32 * 32 * 32 // 32
+        nbytes = {"encode": 4 * (mw + qw), "mul": 4 * (2 * qw + pw), "decode": 4 * (pw + mw), "mont_mul": 12 * mw}
+        row_w = {}
+        for log_n in (20, 22):
+            n = 1 << log_n
+            gen = torch.Generator(device="cuda:0")
+            gen.manual_seed(bits + log_n)
+            a = torch.randint(-2**31, 2**31, (n, mw), dtype=torch.int64, device="cuda:0", generator=gen)
+            a = a.to(torch.int32)
+            top_bits = bits - 32 * (mw - 1)
+            a[:, mw - 1] &= (1 << top_bits) - 1
+            b = torch.randint(-2**31, 2**31, (n, mw), dtype=torch.int64, device="cuda:0", generator=gen).to(torch.int32)
+            b[:, mw - 1] &= (1 << top_bits) - 1
+            xa = torch.empty((n * qw,), dtype=torch.int32, device="cuda:0")
+            xb = torch.empty_like(xa)
+            xp = torch.empty((n * pw,), dtype=torch.int32, device="cuda:0")
+            o = torch.empty_like(a)
+            f.encode(b.data_ptr(), xb.data_ptr(), n, stream)
+            calls = {
+                "encode": lambda: f.encode(a.data_ptr(), xa.data_ptr(), n, stream),
+                "mul": lambda: f.mul(xa.data_ptr(), xb.data_ptr(), xp.data_ptr(), n, stream),
+                "decode": lambda: f.decode(xp.data_ptr(), o.data_ptr(), n, stream),
+                "mont_mul": lambda: f.mont_mul(a.data_ptr(), b.data_ptr(), o.data_ptr(), n, stream),
+            }
+            row = {}
+            for name, fn in calls.items():
+                log(f"f3: {bits} bits 2^{log_n} {name}")
+                t = time_op(torch, fn, steps, 2) * 1e-3
+                row[name] = {"us": round(t * 1e6, 2), "melem_s": round(n / t / 1e6, 1),
+                             "hbm_gbs": round(n * nbytes[name] / t / 1e9, 1)}
+            row["mul"]["mfma_tops"] = round(n * ops / (row["mul"]["us"] * 1e-6) / 1e12, 2)
+
+            def pipeline():
+                calls["encode"]()
+                f.encode(b.data_ptr(), xb.data_ptr(), n, stream)
+                calls["mul"]()
+                calls["decode"]()
+            t = time_op(torch, pipeline, steps, 2) * 1e-3
+            row["pipeline"] = {"us": round(t * 1e6, 2), "melem_s": round(n / t / 1e6, 1)}
+            row["mul_over_mont"] = round(row["mont_mul"]["us"] / row["mul"]["us"], 3)
+            row_w[f"2e{log_n}"] = row
+            del a, b, xa, xb, xp, o
+            torch.cuda.empty_cache()
+        torch.cuda.synchronize()
+        f.close()
+        out[f"{bits}bit"] = row_w
+    return out
+
+
 def bench_c4(ctx, torch, fr, stream, replays):
     """256 forward NTTs, sizes uniform over 2^12..2^20 (seed 4): tune every
     size, capture the persistent batch launch in a hipGraph, time replays."""
@@ -443,8 +505,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing on host cores")
     ap.add_argument("--quick", action="store_true", help="headline config only")
-    ap.add_argument("--only", default="c3,c4,c5,f1,f2",
-                    help="comma list of the other configurations to run (c3, c4, c5, f1, f2)")
+    ap.add_argument("--only", default="c3,c4,c5,f1,f2,f3",
+                    help="comma list of the other configurations to run (c3, c4, c5, f1, f2, f3)")
     ap.add_argument("--c4-replays", type=int, default=200)
     ap.add_argument("--calib", action="store_true",
                     help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
@@ -532,6 +594,8 @@ def main():
         out["f1"] = bench_f1(ctx, torch, fr, stream, max(3, args.steps // 10))
     if "f2" in extra:
         out["f2"] = bench_f2(ctx, torch, fr, stream, max(5, args.steps // 4))
+    if "f3" in extra:
+        out["f3"] = bench_f3(ctx, torch, fr, stream, max(5, args.steps // 4))
     if "c4" in extra:
         out["c4"] = bench_c4(ctx, torch, fr, stream, args.c4_replays)
     if "c5" in extra:
