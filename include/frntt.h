@@ -285,6 +285,38 @@ int frntt_rns_field_decode(frntt_rns_field *f, const void *xp, void *out, int64_
 /* out = a b 2^(-29 L) mod M (L = 9, 13, 26 limbs for 8, 12, 24 words). */
 int frntt_rns_field_mont_mul(frntt_rns_field *f, const void *a, const void *b, void *out, int64_t n, void *stream);
 
+/* ---- multi-scalar multiplication (Background, "Multi-Scalar
+ * Multiplication"; Alg. 2, Layout Stationary Pippenger) ----
+ * MSM = sum_n S_n P_n on the twisted Edwards curve
+ * a x^2 + y^2 = 1 + d x^2 y^2 over Fr, a = 168700, d = 168696 (Baby Jubjub;
+ * the zero point is (0, 1)), with c-bit windows: K = ceil(256 / c) windows of
+ * 2^c buckets.
+ *   scalars: device, n x 8 32-bit little-endian words (any value below
+ *            2^256; not reduced), 16-byte aligned;
+ *   points:  device, n x 16 words: x (8 words) then y (8 words), canonical
+ *            or not (read mod r), 16-byte aligned; points must lie on the
+ *            curve (not checked: other inputs give an unspecified point);
+ *   out:     device, 16 words: the affine result x then y, canonical;
+ *   window:  c in [1, 20], or 0 for frntt_msm_window(n).
+ * n = 0 gives the zero point. The work is queued on `stream` (0: the null
+ * stream) in the context's per-stream scratch (frntt_msm_workspace_bytes;
+ * grown as needed, so not inside a graph capture the first time). Errors:
+ * EINVAL (null pointer, n < 0), ERANGE (n > 2^28, window outside [0, 20]),
+ * EALIGN, ENOMEM, ESTATE (scratch growth during capture), EHIP. */
+int frntt_msm(frntt_ctx *ctx, const void *scalars, const void *points, int64_t n, int window, void *out,
+              void *stream);
+/* Batch scalar multiplication on the same curve: out_i = S_i P_i, affine
+ * (16 words per point: x then y, canonical), n points; the layouts, the
+ * alignment and the on-curve requirement of frntt_msm. out may not overlap
+ * the inputs. Used to produce curve points (multiples of a generator) for
+ * MSM workloads, and as the per-term product of the MSM definition.
+ * Errors: EINVAL, ERANGE (n > 2^28), EALIGN, EHIP. */
+int frntt_ec_mul(frntt_ctx *ctx, const void *scalars, const void *points, int64_t n, void *out, void *stream);
+/* Window width frntt_msm picks for n points (cost model K (n + 5 2^c)). */
+int frntt_msm_window(int64_t n);
+/* Scratch bytes of frntt_msm for (n, window); 0 for arguments it rejects. */
+size_t frntt_msm_workspace_bytes(int64_t n, int window);
+
 /* Last hipError_t seen by the context (0 if none). */
 int frntt_last_hip_error(const frntt_ctx *ctx);
 /* Static description of a status code. */

@@ -85,6 +85,10 @@ SIGNATURES = {
     "frntt_rns_field_mul": (_i, [_vp, _vp, _vp, _vp, ctypes.c_int64, _vp]),
     "frntt_rns_field_decode": (_i, [_vp, _vp, _vp, ctypes.c_int64, _vp]),
     "frntt_rns_field_mont_mul": (_i, [_vp, _vp, _vp, _vp, ctypes.c_int64, _vp]),
+    "frntt_msm": (_i, [_vp, _vp, _vp, ctypes.c_int64, _i, _vp, _vp]),
+    "frntt_msm_window": (_i, [ctypes.c_int64]),
+    "frntt_ec_mul": (_i, [_vp, _vp, _vp, ctypes.c_int64, _vp, _vp]),
+    "frntt_msm_workspace_bytes": (_sz, [ctypes.c_int64, _i]),
 }
 
 RNS_Q_WORDS = 20
@@ -104,6 +108,15 @@ def rns_moduli():
     p = (ctypes.c_uint32 * 9)()
     _check(lib().frntt_rns_moduli(q, p), "frntt_rns_moduli")
     return list(q), list(p)
+
+
+def msm_window(n: int) -> int:
+    """Window width frntt_msm picks for n points (host only)."""
+    return lib().frntt_msm_window(n)
+
+
+def msm_workspace_bytes(n: int, window: int = 0) -> int:
+    return lib().frntt_msm_workspace_bytes(n, window)
 
 
 def library_path() -> str:
@@ -261,6 +274,14 @@ class Context:
 
     def mont_mul(self, a: int, b: int, out: int, n: int, stream: int = 0):
         return _check(lib().frntt_mont_mul(self._h, a, b, out, n, stream), "frntt_mont_mul")
+
+    # multi-scalar multiplication on the twisted Edwards curve over Fr:
+    # scalars n x 8 words, points n x 16 words (x, y), out 16 words (x, y)
+    def msm(self, scalars: int, points: int, n: int, out: int, window: int = 0, stream: int = 0):
+        return _check(lib().frntt_msm(self._h, scalars, points, n, window, out, stream), "frntt_msm")
+
+    def ec_mul(self, scalars: int, points: int, n: int, out: int, stream: int = 0):
+        return _check(lib().frntt_ec_mul(self._h, scalars, points, n, out, stream), "frntt_ec_mul")
 
     def check_inputs(self) -> int:
         return lib().frntt_check_inputs(self._h)
