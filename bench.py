@@ -326,6 +326,58 @@ def bench_f2(ctx, torch, fr, stream, steps):
     return out
 
 
+# Baby Jubjub's published generator of the prime-order subgroup; the MSM
+# workload's points are k_i times it (k_i uniform field elements)
+MSM_BASE = (5299619240641551281634865583518297030282874472190772894086521144482721001553,
+            16950150798460657717958625567821834550301663161624707787222815936182638968203)
+MONT_MADS = 162   # 32x32+64-bit multiply-adds of one 9-limb Montgomery product
+
+
+def msm_products(n, c):
+    """Montgomery products of one MSM of n points with c-bit windows: the
+    point preparation (3 per point), the bucket accumulation (9 per added
+    point), the tree reduction (two additions into W, one addition and one
+    doubling into B per bucket pair and level), and the window merging."""
+    K = -(-256 // c)
+    prep = 3 * n
+    accum = 9 * n * K
+    reduce_ = K * ((1 << c) - 1) * (11 + 11 + 11 + 9)
+    merge = K * (9 * c + 11) + 4
+    return prep + accum + reduce_ + merge
+
+
+def bench_f4(ctx, torch, fr, stream, steps):
+    """Multi-scalar multiplication (Alg. 2, LS-PPG) on the twisted Edwards
+    curve over Fr at 2^20, 2^22 and 2^24 points (the paper's 256-bit MSM runs
+    2^22 to 2^26): milliseconds per MSM, points per second, and the rate of
+    Montgomery-product multiply-adds the whole MSM sustains. Points are k_i G
+    from the batch scalar multiplication, scalars uniform field elements."""
+    out = {}
+    for log_n in (20, 22, 24):
+        n = 1 << log_n
+        k = torch.empty((n, 4), dtype=torch.int64, device="cuda:0")
+        sc = torch.empty_like(k)
+        ctx.generate(k.data_ptr(), 21, 0, 0, n, stream)
+        ctx.generate(sc.data_ptr(), 21, 1, 0, n, stream)
+        g = torch.tensor([[(v >> (32 * i)) & 0xFFFFFFFF for v in MSM_BASE for i in range(8)]],
+                         dtype=torch.int64).to(torch.int32).to("cuda:0")
+        g = g.expand(n, 16).contiguous()
+        pts = torch.empty((n, 16), dtype=torch.int32, device="cuda:0")
+        ctx.ec_mul(k.data_ptr(), g.data_ptr(), n, pts.data_ptr(), stream)
+        del g, k
+        o = torch.empty(16, dtype=torch.int32, device="cuda:0")
+        c = fr.msm_window(n)
+        log(f"f4: msm 2^{log_n} window {c}")
+        t = time_op(torch, lambda: ctx.msm(sc.data_ptr(), pts.data_ptr(), n, o.data_ptr(), 0, stream),
+                    steps, 1) * 1e-3
+        mads = msm_products(n, c) * MONT_MADS
+        out[f"2e{log_n}"] = {"window": c, "ms": round(t * 1e3, 3), "mpoints_s": round(n / t / 1e6, 2),
+                             "tmad_s": round(mads / t / 1e12, 3)}
+        del sc, pts, o
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_f3(ctx, torch, fr, stream, steps):
     """The RNS lazy product against the radix Montgomery product at the wider
     widths the paper evaluates (the largest primes below 2^377 and 2^753), at
@@ -505,8 +557,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing on host cores")
     ap.add_argument("--quick", action="store_true", help="headline config only")
-    ap.add_argument("--only", default="c3,c4,c5,f1,f2,f3",
-                    help="comma list of the other configurations to run (c3, c4, c5, f1, f2, f3)")
+    ap.add_argument("--only", default="c3,c4,c5,f1,f2,f3,f4",
+                    help="comma list of the other configurations to run (c3, c4, c5, f1, f2, f3, f4)")
     ap.add_argument("--c4-replays", type=int, default=200)
     ap.add_argument("--calib", action="store_true",
                     help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
@@ -596,6 +648,8 @@ def main():
         out["f2"] = bench_f2(ctx, torch, fr, stream, max(5, args.steps // 4))
     if "f3" in extra:
         out["f3"] = bench_f3(ctx, torch, fr, stream, max(5, args.steps // 4))
+    if "f4" in extra:
+        out["f4"] = bench_f4(ctx, torch, fr, stream, 3)
     if "c4" in extra:
         out["c4"] = bench_c4(ctx, torch, fr, stream, args.c4_replays)
     if "c5" in extra:
@@ -607,6 +661,8 @@ def main():
     # bound is the unit with the largest fraction of its peak.
     log("measuring the VALU multiply-add and int8 MFMA rates")
     peaks = measure_peaks()
+    for row in out.get("f4", {}).values():
+        row["alu_frac"] = round(row["tmad_s"] / peaks["mad_tps"], 4)
     work = algorithmic_work(mf["plan"])
     launches = len(mf["plan"])
     per_launch_ms = mf["ms"] / launches

@@ -301,7 +301,7 @@ int frntt_rns_field_mont_mul(frntt_rns_field *f, const void *a, const void *b, v
  * n = 0 gives the zero point. The work is queued on `stream` (0: the null
  * stream) in the context's per-stream scratch (frntt_msm_workspace_bytes;
  * grown as needed, so not inside a graph capture the first time). Errors:
- * EINVAL (null pointer, n < 0), ERANGE (n > 2^28, window outside [0, 20]),
+ * EINVAL (null pointer, n < 0), ERANGE (n > 2^26, window outside [0, 20]),
  * EALIGN, ENOMEM, ESTATE (scratch growth during capture), EHIP. */
 int frntt_msm(frntt_ctx *ctx, const void *scalars, const void *points, int64_t n, int window, void *out,
               void *stream);
@@ -310,7 +310,7 @@ int frntt_msm(frntt_ctx *ctx, const void *scalars, const void *points, int64_t n
  * alignment and the on-curve requirement of frntt_msm. out may not overlap
  * the inputs. Used to produce curve points (multiples of a generator) for
  * MSM workloads, and as the per-term product of the MSM definition.
- * Errors: EINVAL, ERANGE (n > 2^28), EALIGN, EHIP. */
+ * Errors: EINVAL, ERANGE (n > 2^26), EALIGN, EHIP. */
 int frntt_ec_mul(frntt_ctx *ctx, const void *scalars, const void *points, int64_t n, void *out, void *stream);
 /* Window width frntt_msm picks for n points (cost model K (n + 5 2^c)). */
 int frntt_msm_window(int64_t n);

@@ -23,6 +23,8 @@
 #include "frntt_internal.hpp"
 #include "host_field.hpp"
 
+#include <rocprim/device/device_radix_sort.hpp>
+
 namespace frntt {
 namespace {
 
@@ -80,8 +82,37 @@ __device__ FRNTT_INLINE ept ept_zero(const MsmConsts& C) {
   return e;
 }
 
+// a x mod r for canonical x and the curve's small a (a < 2^18): the 9-word
+// product v, a quotient estimate q = floor(top 64 bits of v / (r_7 + 1))
+// (never above floor(v / r), and below it by at most one since r_7 is above
+// 2^29), then v - q r < 2r and one conditional subtraction. Montgomery form
+// is kept: a (x 2^261) = (a x) 2^261.
+__device__ FRNTT_INLINE fr_t fr_mul_small(const fr_t& x, uint32_t a) {
+  uint32_t v[9];
+  uint64_t cy = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const uint64_t t = (uint64_t)x.w[i] * a + cy;
+    v[i] = (uint32_t)t;
+    cy = t >> 32;
+  }
+  v[8] = (uint32_t)cy;
+  const uint64_t top = ((uint64_t)v[8] << 32) | v[7];
+  const uint32_t q = (uint32_t)(top / ((uint64_t)FR_R7 + 1));
+  fr_t o;
+  uint64_t mc = 0;
+  uint32_t br = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const uint64_t t = (uint64_t)fr_mod_word(i) * q + mc;
+    mc = t >> 32;
+    o.w[i] = subb(v[i], (uint32_t)t, br, &br);
+  }
+  return fr_reduce_once(o);
+}
+
 // P + (x2, y2) for an affine point given as x2, y2 and d x2 y2 (Montgomery
-// form): the unified addition with Z2 = 1 (9 products).
+// form): the unified addition with Z2 = 1 (8 products and one by a).
 __device__ FRNTT_INLINE ept add_mixed(const ept& P, const fr_t& x2, const fr_t& y2, const fr_t& dt2,
                                       const MsmConsts& C) {
   const fr_t A = mont_mul(P.X, x2);
@@ -90,7 +121,7 @@ __device__ FRNTT_INLINE ept add_mixed(const ept& P, const fr_t& x2, const fr_t& 
   const fr_t E = fr_sub(fr_sub(mont_mul(fr_add(P.X, P.Y), fr_add(x2, y2)), A), B);
   const fr_t F = fr_sub(P.Z, Cc);
   const fr_t G = fr_add(P.Z, Cc);
-  const fr_t H = fr_sub(B, mont_mul(C.a, A));
+  const fr_t H = fr_sub(B, fr_mul_small(A, kCurveA));
   ept o;
   o.X = mont_mul(E, F);
   o.Y = mont_mul(G, H);
@@ -99,7 +130,7 @@ __device__ FRNTT_INLINE ept add_mixed(const ept& P, const fr_t& x2, const fr_t& 
   return o;
 }
 
-// P + Q, the unified addition (11 products).
+// P + Q, the unified addition (10 products).
 __device__ FRNTT_INLINE ept add_full(const ept& P, const ept& Q, const MsmConsts& C) {
   const fr_t A = mont_mul(P.X, Q.X);
   const fr_t B = mont_mul(P.Y, Q.Y);
@@ -108,7 +139,7 @@ __device__ FRNTT_INLINE ept add_full(const ept& P, const ept& Q, const MsmConsts
   const fr_t E = fr_sub(fr_sub(mont_mul(fr_add(P.X, P.Y), fr_add(Q.X, Q.Y)), A), B);
   const fr_t F = fr_sub(D, Cc);
   const fr_t G = fr_add(D, Cc);
-  const fr_t H = fr_sub(B, mont_mul(C.a, A));
+  const fr_t H = fr_sub(B, fr_mul_small(A, kCurveA));
   ept o;
   o.X = mont_mul(E, F);
   o.Y = mont_mul(G, H);
@@ -118,7 +149,7 @@ __device__ FRNTT_INLINE ept add_full(const ept& P, const ept& Q, const MsmConsts
 }
 
 // 2 P, the doubling formula derived from the unified addition (it uses
-// neither T nor d; 9 products): with A = X^2, B = Y^2, G = a A + B, the
+// neither T nor d; 8 products and one by a): with A = X^2, B = Y^2, G = a A + B, the
 // affine result is (2 x y / G, (B - a A) / (2 - G)) scaled by Z^2.
 __device__ FRNTT_INLINE ept dbl(const ept& P, const MsmConsts& C) {
   const fr_t A = mont_mul(P.X, P.X);
@@ -127,7 +158,7 @@ __device__ FRNTT_INLINE ept dbl(const ept& P, const MsmConsts& C) {
   const fr_t Cc = fr_add(Z2, Z2);
   const fr_t XY = fr_add(P.X, P.Y);
   const fr_t E = fr_sub(fr_sub(mont_mul(XY, XY), A), B);
-  const fr_t Da = mont_mul(C.a, A);
+  const fr_t Da = fr_mul_small(A, kCurveA);
   const fr_t G = fr_add(Da, B);
   const fr_t F = fr_sub(G, Cc);
   const fr_t H = fr_sub(Da, B);
@@ -155,13 +186,19 @@ __device__ FRNTT_INLINE void load_scalar(const u32x4* p, uint32_t* s) {
 }
 
 // ---- Bucketize ------------------------------------------------------------
+//
+// The argsort of every window's digits is one radix sort of the pairs
+// (k 2^c + digit, point index) over all windows (rocPRIM's device radix
+// sort); window k's entries then fill positions [k n, (k + 1) n) in digit
+// order, and the bucket bounds are the runs of equal keys.
 
 // Points into Montgomery form with d x y beside them (96 bytes per point),
-// and the histogram of every window's nonzero digits.
+// and the sort's input pairs: key k 2^c + digit at k n + i, value i.
 __global__ __launch_bounds__(kMsmThreads) void msm_prep_kernel(const u32x4* __restrict__ pts,
                                                                const u32x4* __restrict__ sc, int64_t n, int c,
                                                                int K, u32x4* __restrict__ prep,
-                                                               uint32_t* __restrict__ counts, MsmConsts C) {
+                                                               uint32_t* __restrict__ keys,
+                                                               uint32_t* __restrict__ vals, MsmConsts C) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const fr_t xm = mont_mul(load_fr(pts + 4 * i), C.r2);
     const fr_t ym = mont_mul(load_fr(pts + 4 * i + 2), C.r2);
@@ -172,23 +209,105 @@ __global__ __launch_bounds__(kMsmThreads) void msm_prep_kernel(const u32x4* __re
     uint32_t s[8];
     load_scalar(sc + 2 * i, s);
     for (int k = 0; k < K; ++k) {
-      const uint32_t dg = window_digit(s, c, k);
-      if (dg) atomicAdd(counts + ((int64_t)k << c) + dg, 1u);
+      keys[(int64_t)k * n + i] = ((uint32_t)k << c) | window_digit(s, c, k);
+      vals[(int64_t)k * n + i] = (uint32_t)i;
     }
   }
 }
 
-// Exclusive scan of one window's bucket counts (one workgroup per window):
-// the start of each bucket's index list, and a copy the scatter advances.
-__global__ __launch_bounds__(kScanThreads) void msm_scan_kernel(const uint32_t* __restrict__ counts,
-                                                                uint32_t* __restrict__ start,
-                                                                uint32_t* __restrict__ cursor, int c) {
+// Run bounds of the sorted keys: first[key] = start of its run, last[key]
+// = end of its run (both zero for keys that do not occur).
+__global__ __launch_bounds__(kMsmThreads) void msm_bounds_kernel(const uint32_t* __restrict__ keys, int64_t total,
+                                                                 uint32_t* __restrict__ first,
+                                                                 uint32_t* __restrict__ last) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t key = keys[p];
+    if (p == 0 || keys[p - 1] != key) first[key] = (uint32_t)p;
+    if (p == total - 1 || keys[p + 1] != key) last[key] = (uint32_t)(p + 1);
+  }
+}
+
+// Bucket sizes and list starts within each window's list; bucket 0 (digit
+// zero) is left empty, since its points never reach the result.
+__global__ __launch_bounds__(kMsmThreads) void msm_counts_kernel(uint32_t* __restrict__ first,
+                                                                 const uint32_t* __restrict__ last,
+                                                                 uint32_t* __restrict__ counts, int64_t n, int c,
+                                                                 int K) {
+  const int64_t total = (int64_t)K << c;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = g >> c;
+    const uint32_t cnt = (g & ((1 << c) - 1)) ? last[g] - first[g] : 0u;
+    counts[g] = cnt;
+    first[g] = cnt ? (uint32_t)(first[g] - k * n) : 0u;
+  }
+}
+
+// ---- Bucket Accumulation --------------------------------------------------
+//
+// A reduce-by-bucket in levels, so that no thread adds more than a fixed
+// number of terms whatever the digit distribution (a bucket may hold every
+// point, e.g. when all scalars are equal, or a third of them in a top window
+// of two bits). Level 0 cuts each bucket's index list into chunks of kChunk0
+// points and sums each chunk; every further level cuts each bucket's list of
+// partial sums into chunks of kChunk; the last one sums each bucket's (at
+// most kChunk) partials into B_(k,j). Chunks of window k sit at k CW + the
+// exclusive scan of the bucket chunk counts, CW bounding a window's chunks.
+
+constexpr int kChunk0 = 32, kChunk = 32;
+
+// Item i of bucket j's list: a point (x, y, d x y from the prepared array,
+// reached through the index list) or a partial sum.
+struct PointItems {
+  const u32x4* prep;
+  const uint32_t* idx;    // window k's list at idx + k n
+  const uint32_t* start;  // bucket list starts within the window's list
+  int64_t n;
+};
+struct PartialItems {
+  const u32x4* part;      // window k's partials at part + 8 k CW
+  const uint32_t* base;   // bucket partial starts within the window
+  int64_t cw;
+};
+
+// Sum of items [lo, hi) of bucket g (window k), hi > lo
+__device__ FRNTT_INLINE ept sum_items(const PointItems& S, int64_t g, int64_t k, uint32_t lo, uint32_t hi,
+                                      const MsmConsts& C) {
+  const uint32_t* list = S.idx + k * S.n + S.start[g];
+  const u32x4* p0 = S.prep + 6 * (int64_t)list[lo];
+  ept acc;
+  acc.X = load_fr(p0);
+  acc.Y = load_fr(p0 + 2);
+  acc.Z = C.one;
+  acc.T = mont_mul(acc.X, acc.Y);
+  for (uint32_t i = lo + 1; i < hi; ++i) {
+    const u32x4* p = S.prep + 6 * (int64_t)list[i];
+    acc = add_mixed(acc, load_fr(p), load_fr(p + 2), load_fr(p + 4), C);
+  }
+  return acc;
+}
+
+__device__ FRNTT_INLINE ept sum_items(const PartialItems& S, int64_t g, int64_t k, uint32_t lo, uint32_t hi,
+                                      const MsmConsts& C) {
+  const u32x4* list = S.part + 8 * (k * S.cw + S.base[g]);
+  ept acc = load_ept(list + 8 * (int64_t)lo);
+  for (uint32_t i = lo + 1; i < hi; ++i) acc = add_full(acc, load_ept(list + 8 * (int64_t)i), C);
+  return acc;
+}
+
+// Chunk counts ceil(m_j / len) of one window's buckets and their exclusive
+// scan (one workgroup per window).
+__global__ __launch_bounds__(kScanThreads) void msm_chunk_scan_kernel(const uint32_t* __restrict__ m,
+                                                                      uint32_t* __restrict__ nch,
+                                                                      uint32_t* __restrict__ base, int c,
+                                                                      int len) {
   __shared__ uint32_t part[kScanThreads];
-  const int64_t base = (int64_t)blockIdx.x << c;
+  const int64_t w0 = (int64_t)blockIdx.x << c;
   const int nb = 1 << c, per = (nb + kScanThreads - 1) / kScanThreads, t = threadIdx.x;
   const int lo = t * per, hi = lo + per < nb ? lo + per : nb;
   uint32_t s = 0;
-  for (int j = lo; j < hi; ++j) s += counts[base + j];
+  for (int j = lo; j < hi; ++j) s += (m[w0 + j] + len - 1) / len;
   part[t] = s;
   __syncthreads();
   for (int off = 1; off < kScanThreads; off <<= 1) {
@@ -199,55 +318,49 @@ __global__ __launch_bounds__(kScanThreads) void msm_scan_kernel(const uint32_t* 
   }
   uint32_t run = t ? part[t - 1] : 0u;
   for (int j = lo; j < hi; ++j) {
-    start[base + j] = run;
-    cursor[base + j] = run;
-    run += counts[base + j];
+    const uint32_t q = (m[w0 + j] + len - 1) / len;
+    base[w0 + j] = run;
+    nch[w0 + j] = q;
+    run += q;
   }
 }
 
-// Each point's index into the list of its bucket in every window.
-__global__ __launch_bounds__(kMsmThreads) void msm_scatter_kernel(const u32x4* __restrict__ sc, int64_t n, int c,
-                                                                  int K, uint32_t* __restrict__ cursor,
-                                                                  uint32_t* __restrict__ idx) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    uint32_t s[8];
-    load_scalar(sc + 2 * i, s);
-    for (int k = 0; k < K; ++k) {
-      const uint32_t dg = window_digit(s, c, k);
-      if (dg) {
-        const uint32_t pos = atomicAdd(cursor + ((int64_t)k << c) + dg, 1u);
-        idx[(int64_t)k * n + pos] = (uint32_t)i;
-      }
+// One level: chunk q of window k (thread per chunk slot) sums items
+// [r len, min(r len + len, m_j)) of its bucket j, r = q - base_j.
+template <class Items>
+__global__ __launch_bounds__(kMsmThreads) void msm_chunk_kernel(Items S, const uint32_t* __restrict__ m_in,
+                                                                const uint32_t* __restrict__ nch,
+                                                                const uint32_t* __restrict__ base, int c, int K,
+                                                                int len, int64_t cw_out,
+                                                                u32x4* __restrict__ out, MsmConsts C) {
+  const int64_t total = (int64_t)K * cw_out;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = g / cw_out, q = g - k * cw_out, w0 = k << c, last = w0 + (1 << c) - 1;
+    if (q >= (int64_t)base[last] + nch[last]) continue;
+    // the bucket whose chunks contain q: the last j with base_j <= q
+    int64_t lo = w0, hi = last + 1;
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if ((int64_t)base[mid] <= q) lo = mid;
+      else hi = mid;
     }
+    const uint32_t r = (uint32_t)(q - base[lo]), first = r * (uint32_t)len;
+    const uint32_t end = m_in[lo] - first < (uint32_t)len ? m_in[lo] : first + (uint32_t)len;
+    store_ept(out + 8 * g, sum_items(S, lo, k, first, end, C));
   }
 }
 
-// ---- Bucket Accumulation --------------------------------------------------
-
-// B_(k,j) = sum of the points in bucket (k, j); one bucket per thread. The
-// first point of a bucket is taken as it is (T = x y), the rest are added.
-__global__ __launch_bounds__(kMsmThreads) void msm_accum_kernel(const u32x4* __restrict__ prep,
-                                                                const uint32_t* __restrict__ idx,
-                                                                const uint32_t* __restrict__ start,
-                                                                const uint32_t* __restrict__ counts, int64_t n,
-                                                                int c, int K, u32x4* __restrict__ B, MsmConsts C) {
+// Last level: B_(k,j) = the sum of bucket j's (at most a chunk of) items, or
+// the zero point for an empty bucket; one bucket per thread.
+template <class Items>
+__global__ __launch_bounds__(kMsmThreads) void msm_bucket_kernel(Items S, const uint32_t* __restrict__ m_in, int c,
+                                                                 int K, u32x4* __restrict__ B, MsmConsts C) {
   const int64_t total = (int64_t)K << c;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
        g += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t cnt = counts[g];
-    ept acc = ept_zero(C);
-    if (cnt) {
-      const uint32_t* list = idx + (g >> c) * n + start[g];
-      const u32x4* p0 = prep + 6 * (int64_t)list[0];
-      acc.X = load_fr(p0);
-      acc.Y = load_fr(p0 + 2);
-      acc.T = mont_mul(acc.X, acc.Y);
-      for (uint32_t i = 1; i < cnt; ++i) {
-        const u32x4* p = prep + 6 * (int64_t)list[i];
-        acc = add_mixed(acc, load_fr(p), load_fr(p + 2), load_fr(p + 4), C);
-      }
-    }
-    store_ept(B + 8 * g, acc);
+    const uint32_t cnt = m_in[g];
+    store_ept(B + 8 * g, cnt ? sum_items(S, g, g >> c, 0, cnt, C) : ept_zero(C));
   }
 }
 
@@ -369,25 +482,109 @@ __device__ fr_t fr_inverse(const fr_t& a) {
   return o;
 }
 
-// MSM = sum_k 2^(c k) W_k from the top window down, then (x, y) = (X/Z, Y/Z)
-// in canonical form: out[0..7] = x, out[8..15] = y.
+// Lane-parallel forms of the doubling and the addition for the serial
+// window merging: the independent products of each step run on separate
+// lanes of one wave (lane l takes product min(l, n - 1) of the step), and
+// every lane reads all of them back, so that the state stays replicated.
+__device__ FRNTT_INLINE fr_t read_lane(const fr_t& x, int l) {
+  fr_t o;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) o.w[i] = (uint32_t)__builtin_amdgcn_readlane((int)x.w[i], l);
+  return o;
+}
+
+__device__ FRNTT_INLINE fr_t pick(int l, const fr_t& a0, const fr_t& a1, const fr_t& a2, const fr_t& a3) {
+  fr_t o;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) o.w[i] = l == 0 ? a0.w[i] : l == 1 ? a1.w[i] : l == 2 ? a2.w[i] : a3.w[i];
+  return o;
+}
+
+// X3 = E F, Y3 = G H, Z3 = F G, T3 = E H on lanes 0..3
+__device__ FRNTT_INLINE ept finish_lanes(int lane, const fr_t& E, const fr_t& F, const fr_t& G, const fr_t& H) {
+  const int l = lane < 3 ? lane : 3;
+  const fr_t r = mont_mul(pick(l, E, G, F, E), pick(l, F, H, G, H));
+  ept o;
+  o.X = read_lane(r, 0);
+  o.Y = read_lane(r, 1);
+  o.Z = read_lane(r, 2);
+  o.T = read_lane(r, 3);
+  return o;
+}
+
+__device__ FRNTT_INLINE ept dbl_lanes(int lane, const ept& P) {
+  const int l = lane < 3 ? lane : 3;
+  const fr_t xy = fr_add(P.X, P.Y);
+  const fr_t s = pick(l, P.X, P.Y, P.Z, xy);
+  const fr_t r = mont_mul(s, s);
+  const fr_t A = read_lane(r, 0), B = read_lane(r, 1), Z2 = read_lane(r, 2), S = read_lane(r, 3);
+  const fr_t E = fr_sub(fr_sub(S, A), B);
+  const fr_t Da = fr_mul_small(A, kCurveA);
+  const fr_t G = fr_add(Da, B);
+  const fr_t F = fr_sub(G, fr_add(Z2, Z2));
+  const fr_t H = fr_sub(Da, B);
+  return finish_lanes(lane, E, F, G, H);
+}
+
+// P + Q with d T_Q given
+__device__ FRNTT_INLINE ept add_lanes(int lane, const ept& P, const ept& Q, const fr_t& dTQ) {
+  const int l = lane < 4 ? lane : 4;
+  fr_t a, b;
+  if (l == 4) {
+    a = fr_add(P.X, P.Y);
+    b = fr_add(Q.X, Q.Y);
+  } else {
+    a = pick(l, P.X, P.Y, P.T, P.Z);
+    b = pick(l, Q.X, Q.Y, dTQ, Q.Z);
+  }
+  const fr_t r = mont_mul(a, b);
+  const fr_t A = read_lane(r, 0), B = read_lane(r, 1), Cc = read_lane(r, 2), D = read_lane(r, 3);
+  const fr_t E = fr_sub(fr_sub(read_lane(r, 4), A), B);
+  const fr_t F = fr_sub(D, Cc);
+  const fr_t G = fr_add(D, Cc);
+  const fr_t H = fr_sub(B, fr_mul_small(A, kCurveA));
+  return finish_lanes(lane, E, F, G, H);
+}
+
+constexpr int kMergeMaxK = 256;
+
+// MSM = sum_k 2^(c k) W_k from the top window down (one wave; the W_k and
+// their d T are staged in LDS first), then (x, y) = (X/Z, Y/Z) in canonical
+// form: out[0..7] = x, out[8..15] = y.
 __global__ __launch_bounds__(64) void msm_merge_kernel(const u32x4* __restrict__ W, int c, int K,
                                                        uint32_t* __restrict__ out, MsmConsts C) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  __shared__ fr_t sw[kMergeMaxK][5];
+  const int lane = threadIdx.x;
+  for (int k = lane; k < K; k += 64) {
+    const ept w = load_ept(W + 8 * ((int64_t)k << c));
+    sw[k][0] = w.X;
+    sw[k][1] = w.Y;
+    sw[k][2] = w.Z;
+    sw[k][3] = w.T;
+    sw[k][4] = mont_mul(w.T, C.d);
+  }
+  __syncthreads();
   ept acc = ept_zero(C);
   for (int k = K - 1; k >= 0; --k) {
     if (k != K - 1)
-      for (int i = 0; i < c; ++i) acc = dbl(acc, C);
-    acc = add_full(acc, load_ept(W + 8 * ((int64_t)k << c)), C);
+      for (int i = 0; i < c; ++i) acc = dbl_lanes(lane, acc);
+    ept w;
+    w.X = sw[k][0];
+    w.Y = sw[k][1];
+    w.Z = sw[k][2];
+    w.T = sw[k][3];
+    acc = add_lanes(lane, acc, w, sw[k][4]);
   }
   fr_t one_c = fr_zero();
   one_c.w[0] = 1;
   const fr_t zi = fr_inverse(mont_mul(acc.Z, one_c));
   const fr_t x = mont_mul(acc.X, zi), y = mont_mul(acc.Y, zi);
+  if (lane == 0) {
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    out[i] = x.w[i];
-    out[8 + i] = y.w[i];
+    for (int i = 0; i < 8; ++i) {
+      out[i] = x.w[i];
+      out[8 + i] = y.w[i];
+    }
   }
 }
 
@@ -453,18 +650,68 @@ struct MsmDeviceGuard {
 };
 
 constexpr int kMsmMaxWindow = 20;
-constexpr int64_t kMsmMaxPoints = (int64_t)1 << 28;
+constexpr int64_t kMsmMaxPoints = (int64_t)1 << 26;
 
 int windows_for(int c) { return (256 + c - 1) / c; }
 
-// Workspace: prepared points, counts, starts, cursors, index lists, and two
-// (B, W) buffer pairs of K 2^c extended points.
-size_t msm_workspace_bytes(int64_t n, int c) {
-  const size_t K = (size_t)windows_for(c), nb = K << c;
-  const size_t prep = (size_t)n * 96, cnt = nb * 4 * 3, idx = K * (size_t)n * 4, pts = nb * 128 * 4;
-  const auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
-  return up(prep) + up(cnt) + up(idx) + up(pts);
+// Chunk-slot bounds CW of the accumulation levels: level 0 has at most
+// ceil(n / kChunk0) + 2^c chunks per window, each further level at most
+// CW_prev / kChunk + 2^c, until no bucket can have more than kChunk partials.
+// Returns the level count (0: the buckets are summed from the points
+// directly, n <= kChunk0).
+int chunk_levels(int64_t n, int c, int64_t* cw) {
+  if (n <= kChunk0) return 0;
+  int lv = 0;
+  int64_t bound = (n + kChunk0 - 1) / kChunk0;
+  cw[lv++] = bound + ((int64_t)1 << c);
+  while (bound > kChunk) {
+    bound = (bound + kChunk - 1) / kChunk;
+    cw[lv] = (cw[lv - 1] + kChunk - 1) / kChunk + ((int64_t)1 << c);
+    ++lv;
+  }
+  return lv;
 }
+
+constexpr int kMaxChunkLevels = 8;
+
+struct MsmLayout {
+  size_t prep, cnt, idx, sort, sort_tmp, part, pts, total;
+  unsigned key_bits;
+  int64_t cw[kMaxChunkLevels];
+  int levels;
+  int64_t cw_max;
+};
+
+// Workspace: prepared points; counts, run starts and ends, plus two
+// (chunk count, chunk start) array pairs; the sorted index lists; the sort's
+// input keys, output keys and input values, and its temporary storage; two
+// partial-sum buffers of K CW_max points; two (B, W) buffer pairs of K 2^c
+// points.
+MsmLayout msm_layout(int64_t n, int c) {
+  MsmLayout L;
+  const size_t K = (size_t)windows_for(c), nb = K << c;
+  L.levels = chunk_levels(n, c, L.cw);
+  L.cw_max = 0;
+  for (int i = 0; i < L.levels; ++i) L.cw_max = L.cw[i] > L.cw_max ? L.cw[i] : L.cw_max;
+  const auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  L.prep = up((size_t)n * 96);
+  L.cnt = up(nb * 4 * 7);
+  L.idx = up(K * (size_t)n * 4);
+  L.sort = 3 * L.idx;
+  L.key_bits = 0;
+  while (((size_t)1 << L.key_bits) < nb) ++L.key_bits;
+  size_t tmp = 0;
+  (void)rocprim::radix_sort_pairs(nullptr, tmp, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                  (const uint32_t*)nullptr, (uint32_t*)nullptr, K * (size_t)n, 0u,
+                                  L.key_bits);
+  L.sort_tmp = up(tmp);
+  L.part = up(2 * K * (size_t)L.cw_max * 128);
+  L.pts = up(nb * 128 * 4);
+  L.total = L.prep + L.cnt + L.idx + L.sort + L.sort_tmp + L.part + L.pts;
+  return L;
+}
+
+size_t msm_workspace_bytes(int64_t n, int c) { return msm_layout(n, c).total; }
 
 int grid_of(const frntt_ctx* ctx, int64_t items, bool capped) {
   int64_t g = (items + kMsmThreads - 1) / kMsmThreads;
@@ -523,30 +770,74 @@ int frntt_msm(frntt_ctx* ctx, const void* scalars, const void* points, int64_t n
     return msm_status(ctx);
   }
   const int64_t nb = (int64_t)K << c;
+  const MsmLayout lay = msm_layout(n, c);
   void* ws = nullptr;
-  int rc = get_scratch(ctx, st, msm_workspace_bytes(n, c), &ws);
+  int rc = get_scratch(ctx, st, lay.total, &ws);
   if (rc != FRNTT_OK) return rc;
-  const auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
   char* p = (char*)ws;
   u32x4* prep = (u32x4*)p;
-  p += up((size_t)n * 96);
+  p += lay.prep;
   uint32_t* counts = (uint32_t*)p;
   uint32_t* start = counts + nb;
   uint32_t* cursor = start + nb;
-  p += up((size_t)nb * 12);
+  uint32_t* mA = cursor + nb;
+  uint32_t* baseA = mA + nb;
+  uint32_t* mB = baseA + nb;
+  uint32_t* baseB = mB + nb;
+  p += lay.cnt;
   uint32_t* idx = (uint32_t*)p;
-  p += up((size_t)K * n * 4);
+  p += lay.idx;
+  uint32_t* keys_in = (uint32_t*)p;
+  uint32_t* keys_out = (uint32_t*)(p + lay.idx);
+  uint32_t* vals_in = (uint32_t*)(p + 2 * lay.idx);
+  p += lay.sort;
+  void* sort_tmp = p;
+  p += lay.sort_tmp;
+  u32x4* PA = (u32x4*)p;
+  u32x4* PB = PA + 8 * (int64_t)K * lay.cw_max;
+  p += lay.part;
   u32x4* B0 = (u32x4*)p;
   u32x4* W0 = B0 + 8 * nb;
   u32x4* B1 = W0 + 8 * nb;
   u32x4* W1 = B1 + 8 * nb;
 
-  zero_words_kernel<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(counts, nb);
-  msm_prep_kernel<<<grid_of(ctx, n, true), kMsmThreads, 0, st>>>((const u32x4*)points, (const u32x4*)scalars, n,
-                                                                  c, K, prep, counts, C);
-  msm_scan_kernel<<<K, kScanThreads, 0, st>>>(counts, start, cursor, c);
-  msm_scatter_kernel<<<grid_of(ctx, n, true), kMsmThreads, 0, st>>>((const u32x4*)scalars, n, c, K, cursor, idx);
-  msm_accum_kernel<<<grid_of(ctx, nb, false), kMsmThreads, 0, st>>>(prep, idx, start, counts, n, c, K, B0, C);
+  const int64_t total = (int64_t)K * n;
+  zero_words_kernel<<<(unsigned)((2 * nb + 255) / 256), 256, 0, st>>>(start, 2 * nb);
+  msm_prep_kernel<<<grid_of(ctx, n, false), kMsmThreads, 0, st>>>((const u32x4*)points, (const u32x4*)scalars, n,
+                                                                   c, K, prep, keys_in, vals_in, C);
+  size_t tmp_bytes = lay.sort_tmp;
+  const hipError_t se = rocprim::radix_sort_pairs(sort_tmp, tmp_bytes, (const uint32_t*)keys_in, keys_out,
+                                                  (const uint32_t*)vals_in, idx, (size_t)total, 0u, lay.key_bits,
+                                                  st);
+  if (se != hipSuccess) return set_hip_error(ctx, se);
+  msm_bounds_kernel<<<grid_of(ctx, total, true), kMsmThreads, 0, st>>>(keys_out, total, start, cursor);
+  msm_counts_kernel<<<grid_of(ctx, nb, false), kMsmThreads, 0, st>>>(start, cursor, counts, n, c, K);
+  const PointItems pts_items{prep, idx, start, n};
+  if (lay.levels == 0) {
+    msm_bucket_kernel<PointItems><<<grid_of(ctx, nb, false), kMsmThreads, 0, st>>>(pts_items, counts, c, K, B0, C);
+  } else {
+    msm_chunk_scan_kernel<<<K, kScanThreads, 0, st>>>(counts, mA, baseA, c, kChunk0);
+    msm_chunk_kernel<PointItems><<<grid_of(ctx, (int64_t)K * lay.cw[0], false), kMsmThreads, 0, st>>>(
+        pts_items, counts, mA, baseA, c, K, kChunk0, lay.cw[0], PA, C);
+    uint32_t *m_in = mA, *b_in = baseA, *m_out = mB, *b_out = baseB;
+    u32x4 *src = PA, *dst = PB;
+    for (int lv = 1; lv < lay.levels; ++lv) {
+      msm_chunk_scan_kernel<<<K, kScanThreads, 0, st>>>(m_in, m_out, b_out, c, kChunk);
+      msm_chunk_kernel<PartialItems><<<grid_of(ctx, (int64_t)K * lay.cw[lv], false), kMsmThreads, 0, st>>>(
+          PartialItems{src, b_in, lay.cw[lv - 1]}, m_in, m_out, b_out, c, K, kChunk, lay.cw[lv], dst, C);
+      uint32_t* t = m_in;
+      m_in = m_out;
+      m_out = t;
+      t = b_in;
+      b_in = b_out;
+      b_out = t;
+      u32x4* tp = src;
+      src = dst;
+      dst = tp;
+    }
+    msm_bucket_kernel<PartialItems><<<grid_of(ctx, nb, false), kMsmThreads, 0, st>>>(
+        PartialItems{src, b_in, lay.cw[lay.levels - 1]}, m_in, c, K, B0, C);
+  }
   u32x4 *bi = B0, *wi = W0, *bo = B1, *wo = W1;
   for (int s = c - 1; s >= 0; --s) {
     msm_reduce_kernel<<<grid_of(ctx, (int64_t)K << s, false), kMsmThreads, 0, st>>>(bi, wi, bo, wo, c, K, s,

@@ -174,6 +174,25 @@ def test_msm_walk_points_closed_form(ctx, n, window):
     assert _msm(ctx, sc, pts, window) == _walk_expected(sc, bases, h)
 
 
+@pytest.mark.parametrize("kind", ["equal", "top_bits", "small"])
+def test_msm_skewed_digits(ctx, kind):
+    # buckets far above the mean size: every point in one bucket per window,
+    # a third of the points in each of three top-window buckets, or only the
+    # low windows in use
+    n = 40000
+    pts, bases, h = _walk_points(n, 1000)
+    rnd = np.random.default_rng(5)
+    if kind == "equal":
+        sc = [0x1234567890ABCDEF1234567890ABCDEF] * n
+    elif kind == "top_bits":
+        sc = [int(v) << 252 for v in rnd.integers(1, 4, n)]
+    else:
+        sc = [int(v) for v in rnd.integers(0, 1 << 20, n)]
+    for window in (0, 14):
+        _say(f"msm skewed {kind} n={n} window={window or fr.msm_window(n)}")
+        assert _msm(ctx, sc, pts, window) == _walk_expected(sc, bases, h)
+
+
 def test_ec_mul_matches_oracle(ctx):
     n = 40
     pts = _rand_points(n, 900)
