@@ -296,32 +296,97 @@ __device__ FRNTT_INLINE ept sum_items(const PartialItems& S, int64_t g, int64_t 
   return acc;
 }
 
-// Chunk counts ceil(m_j / len) of one window's buckets and their exclusive
-// scan (one workgroup per window).
-__global__ __launch_bounds__(kScanThreads) void msm_chunk_scan_kernel(const uint32_t* __restrict__ m,
-                                                                      uint32_t* __restrict__ nch,
-                                                                      uint32_t* __restrict__ base, int c,
-                                                                      int len) {
-  __shared__ uint32_t part[kScanThreads];
-  const int64_t w0 = (int64_t)blockIdx.x << c;
-  const int nb = 1 << c, per = (nb + kScanThreads - 1) / kScanThreads, t = threadIdx.x;
-  const int lo = t * per, hi = lo + per < nb ? lo + per : nb;
-  uint32_t s = 0;
-  for (int j = lo; j < hi; ++j) s += (m[w0 + j] + len - 1) / len;
-  part[t] = s;
+// Chunk counts of one level and their exclusive scan within each window, in
+// tiles of kTile buckets: a tile-sum launch, then a launch in which every
+// tile adds the sums of the window's earlier tiles to its own block scan.
+// Level 0 cuts every bucket (ceil(m / len)); a later level only the buckets
+// with more than len partials (the others are final after the level before).
+constexpr int kTile = 1024, kTileThreads = 256;
+
+__device__ FRNTT_INLINE uint32_t chunk_count(uint32_t m, int len, int heavy_only) {
+  return heavy_only && m <= (uint32_t)len ? 0u : (m + (uint32_t)len - 1) / (uint32_t)len;
+}
+
+__device__ FRNTT_INLINE uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += (uint32_t)__shfl_xor((int)v, off);
+  return v;
+}
+
+// sum over the block (kTileThreads threads), returned to every thread
+__device__ FRNTT_INLINE uint32_t block_sum(uint32_t v, uint32_t* lds) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) lds[w] = v;
   __syncthreads();
-  for (int off = 1; off < kScanThreads; off <<= 1) {
-    const uint32_t v = t >= off ? part[t - off] : 0u;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
+  uint32_t r = 0;
+#pragma unroll
+  for (int i = 0; i < kTileThreads / 64; ++i) r += lds[i];
+  __syncthreads();
+  return r;
+}
+
+// exclusive prefix over the block in thread order
+__device__ FRNTT_INLINE uint32_t block_exclusive(uint32_t v, uint32_t* lds) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t inc = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t t = (uint32_t)__shfl_up((int)inc, off);
+    if (lane >= off) inc += t;
   }
-  uint32_t run = t ? part[t - 1] : 0u;
-  for (int j = lo; j < hi; ++j) {
-    const uint32_t q = (m[w0 + j] + len - 1) / len;
-    base[w0 + j] = run;
-    nch[w0 + j] = q;
-    run += q;
+  if (lane == 63) lds[w] = inc;
+  __syncthreads();
+  uint32_t pre = 0;
+  for (int i = 0; i < w; ++i) pre += lds[i];
+  __syncthreads();
+  return pre + inc - v;
+}
+
+__device__ FRNTT_INLINE int tiles_per_window(int c) { return c > 10 ? 1 << (c - 10) : 1; }
+
+__global__ __launch_bounds__(kTileThreads) void msm_tile_sum_kernel(const uint32_t* __restrict__ m,
+                                                                    uint32_t* __restrict__ tsum, int c, int len,
+                                                                    int heavy_only) {
+  __shared__ uint32_t lds[kTileThreads / 64];
+  const int tiles = tiles_per_window(c), nb = 1 << c;
+  const int64_t tile = blockIdx.x, k = tile / tiles;
+  const int lo = (int)(tile - k * tiles) * kTile;
+  uint32_t s = 0;
+  for (int e = threadIdx.x; e < kTile && lo + e < nb; e += kTileThreads)
+    s += chunk_count(m[(k << c) + lo + e], len, heavy_only);
+  s = block_sum(s, lds);
+  if (threadIdx.x == 0) tsum[tile] = s;
+}
+
+__global__ __launch_bounds__(kTileThreads) void msm_tile_scan_kernel(const uint32_t* __restrict__ m,
+                                                                     const uint32_t* __restrict__ tsum,
+                                                                     uint32_t* __restrict__ nch,
+                                                                     uint32_t* __restrict__ base, int c, int len,
+                                                                     int heavy_only) {
+  __shared__ uint32_t lds[kTileThreads / 64];
+  const int tiles = tiles_per_window(c), nb = 1 << c;
+  const int64_t tile = blockIdx.x, k = tile / tiles, t = tile - k * tiles;
+  const int lo = (int)t * kTile;
+  uint32_t pre = 0;
+  for (int64_t e = threadIdx.x; e < t; e += kTileThreads) pre += tsum[k * tiles + e];
+  pre = block_sum(pre, lds);
+  constexpr int kPer = kTile / kTileThreads;
+  const int j0 = lo + kPer * threadIdx.x;
+  uint32_t v[kPer], loc = 0;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    v[q] = j0 + q < nb ? chunk_count(m[(k << c) + j0 + q], len, heavy_only) : 0u;
+    loc += v[q];
+  }
+  uint32_t run = pre + block_exclusive(loc, lds);
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    if (j0 + q < nb) {
+      base[(k << c) + j0 + q] = run;
+      nch[(k << c) + j0 + q] = v[q];
+      run += v[q];
+    }
   }
 }
 
@@ -351,16 +416,45 @@ __global__ __launch_bounds__(kMsmThreads) void msm_chunk_kernel(Items S, const u
   }
 }
 
-// Last level: B_(k,j) = the sum of bucket j's (at most a chunk of) items, or
-// the zero point for an empty bucket; one bucket per thread.
-template <class Items>
-__global__ __launch_bounds__(kMsmThreads) void msm_bucket_kernel(Items S, const uint32_t* __restrict__ m_in, int c,
-                                                                 int K, u32x4* __restrict__ B, MsmConsts C) {
+// Without chunk levels (n <= kChunk0): B_(k,j) = the sum of bucket j's
+// points, or the zero point for an empty bucket; one bucket per thread.
+__global__ __launch_bounds__(kMsmThreads) void msm_bucket_points_kernel(PointItems S,
+                                                                        const uint32_t* __restrict__ counts, int c,
+                                                                        int K, u32x4* __restrict__ B, MsmConsts C) {
   const int64_t total = (int64_t)K << c;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
        g += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t cnt = m_in[g];
+    const uint32_t cnt = counts[g];
     store_ept(B + 8 * g, cnt ? sum_items(S, g, g >> c, 0, cnt, C) : ept_zero(C));
+  }
+}
+
+constexpr int kMaxChunkLevels = 8;
+
+// The partial sums of every chunk level: level l's chunk counts and starts
+// per bucket and its partials (window k at part + 8 k cw).
+struct ChunkLevels {
+  const u32x4* part[kMaxChunkLevels];
+  const uint32_t* m[kMaxChunkLevels];
+  const uint32_t* base[kMaxChunkLevels];
+  int64_t cw[kMaxChunkLevels];
+  int levels;
+};
+
+// B_(k,j) = the sum of bucket j's partials at the first level where they
+// fit one chunk (level 0 for all but the buckets that are far above the
+// mean size), or the zero point; one bucket per thread.
+__global__ __launch_bounds__(kMsmThreads) void msm_bucket_final_kernel(ChunkLevels L, int c, int K,
+                                                                       u32x4* __restrict__ B, MsmConsts C) {
+  const int64_t total = (int64_t)K << c;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    int lv = 0;
+    uint32_t cnt = L.m[0][g];
+    while (cnt > (uint32_t)kChunk && lv + 1 < L.levels) cnt = L.m[++lv][g];
+    ept acc = ept_zero(C);
+    if (cnt) acc = sum_items(PartialItems{L.part[lv], L.base[lv], L.cw[lv]}, g, g >> c, 0, cnt, C);
+    store_ept(B + 8 * g, acc);
   }
 }
 
@@ -655,10 +749,11 @@ constexpr int64_t kMsmMaxPoints = (int64_t)1 << 26;
 int windows_for(int c) { return (256 + c - 1) / c; }
 
 // Chunk-slot bounds CW of the accumulation levels: level 0 has at most
-// ceil(n / kChunk0) + 2^c chunks per window, each further level at most
-// CW_prev / kChunk + 2^c, until no bucket can have more than kChunk partials.
-// Returns the level count (0: the buckets are summed from the points
-// directly, n <= kChunk0).
+// ceil(n / kChunk0) + 2^c chunks per window; a later level cuts only buckets
+// with more than kChunk partials, into fewer than a sixteenth as many
+// chunks, so at most CW_prev / 16 + 1. Levels are added until no bucket can
+// have more than kChunk partials. Returns the level count (0: the buckets
+// are summed from the points directly, n <= kChunk0).
 int chunk_levels(int64_t n, int c, int64_t* cw) {
   if (n <= kChunk0) return 0;
   int lv = 0;
@@ -666,36 +761,38 @@ int chunk_levels(int64_t n, int c, int64_t* cw) {
   cw[lv++] = bound + ((int64_t)1 << c);
   while (bound > kChunk) {
     bound = (bound + kChunk - 1) / kChunk;
-    cw[lv] = (cw[lv - 1] + kChunk - 1) / kChunk + ((int64_t)1 << c);
+    cw[lv] = cw[lv - 1] / 16 + 1;
     ++lv;
   }
   return lv;
 }
 
-constexpr int kMaxChunkLevels = 8;
-
 struct MsmLayout {
-  size_t prep, cnt, idx, sort, sort_tmp, part, pts, total;
+  size_t prep, cnt, lvl, idx, sort, sort_tmp, part, pts, total;
   unsigned key_bits;
   int64_t cw[kMaxChunkLevels];
+  int64_t part_off[kMaxChunkLevels];  // first partial of each level (points)
   int levels;
-  int64_t cw_max;
 };
 
-// Workspace: prepared points; counts, run starts and ends, plus two
-// (chunk count, chunk start) array pairs; the sorted index lists; the sort's
-// input keys, output keys and input values, and its temporary storage; two
-// partial-sum buffers of K CW_max points; two (B, W) buffer pairs of K 2^c
-// points.
+// Workspace: prepared points; counts, run starts and ends, tile sums; the
+// chunk counts and starts of every level; the sorted index lists; the
+// sort's input keys, output keys and input values, and its temporary
+// storage; the partial sums of every level; two (B, W) buffer pairs of
+// K 2^c points.
 MsmLayout msm_layout(int64_t n, int c) {
   MsmLayout L;
   const size_t K = (size_t)windows_for(c), nb = K << c;
   L.levels = chunk_levels(n, c, L.cw);
-  L.cw_max = 0;
-  for (int i = 0; i < L.levels; ++i) L.cw_max = L.cw[i] > L.cw_max ? L.cw[i] : L.cw_max;
+  int64_t off = 0;
+  for (int i = 0; i < L.levels; ++i) {
+    L.part_off[i] = off;
+    off += (int64_t)K * L.cw[i];
+  }
   const auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
   L.prep = up((size_t)n * 96);
-  L.cnt = up(nb * 4 * 7);
+  L.cnt = up(nb * 4 * 4);
+  L.lvl = up(nb * 4 * 2 * (size_t)L.levels);
   L.idx = up(K * (size_t)n * 4);
   L.sort = 3 * L.idx;
   L.key_bits = 0;
@@ -705,9 +802,9 @@ MsmLayout msm_layout(int64_t n, int c) {
                                   (const uint32_t*)nullptr, (uint32_t*)nullptr, K * (size_t)n, 0u,
                                   L.key_bits);
   L.sort_tmp = up(tmp);
-  L.part = up(2 * K * (size_t)L.cw_max * 128);
+  L.part = up((size_t)off * 128);
   L.pts = up(nb * 128 * 4);
-  L.total = L.prep + L.cnt + L.idx + L.sort + L.sort_tmp + L.part + L.pts;
+  L.total = L.prep + L.cnt + L.lvl + L.idx + L.sort + L.sort_tmp + L.part + L.pts;
   return L;
 }
 
@@ -779,12 +876,11 @@ int frntt_msm(frntt_ctx* ctx, const void* scalars, const void* points, int64_t n
   p += lay.prep;
   uint32_t* counts = (uint32_t*)p;
   uint32_t* start = counts + nb;
-  uint32_t* cursor = start + nb;
-  uint32_t* mA = cursor + nb;
-  uint32_t* baseA = mA + nb;
-  uint32_t* mB = baseA + nb;
-  uint32_t* baseB = mB + nb;
+  uint32_t* ends = start + nb;
+  uint32_t* tsum = ends + nb;
   p += lay.cnt;
+  uint32_t* lvl = (uint32_t*)p;  // level l: chunk counts at 2 l nb, starts at (2 l + 1) nb
+  p += lay.lvl;
   uint32_t* idx = (uint32_t*)p;
   p += lay.idx;
   uint32_t* keys_in = (uint32_t*)p;
@@ -793,8 +889,7 @@ int frntt_msm(frntt_ctx* ctx, const void* scalars, const void* points, int64_t n
   p += lay.sort;
   void* sort_tmp = p;
   p += lay.sort_tmp;
-  u32x4* PA = (u32x4*)p;
-  u32x4* PB = PA + 8 * (int64_t)K * lay.cw_max;
+  u32x4* part = (u32x4*)p;
   p += lay.part;
   u32x4* B0 = (u32x4*)p;
   u32x4* W0 = B0 + 8 * nb;
@@ -810,33 +905,37 @@ int frntt_msm(frntt_ctx* ctx, const void* scalars, const void* points, int64_t n
                                                   (const uint32_t*)vals_in, idx, (size_t)total, 0u, lay.key_bits,
                                                   st);
   if (se != hipSuccess) return set_hip_error(ctx, se);
-  msm_bounds_kernel<<<grid_of(ctx, total, true), kMsmThreads, 0, st>>>(keys_out, total, start, cursor);
-  msm_counts_kernel<<<grid_of(ctx, nb, false), kMsmThreads, 0, st>>>(start, cursor, counts, n, c, K);
+  msm_bounds_kernel<<<grid_of(ctx, total, true), kMsmThreads, 0, st>>>(keys_out, total, start, ends);
+  msm_counts_kernel<<<grid_of(ctx, nb, false), kMsmThreads, 0, st>>>(start, ends, counts, n, c, K);
   const PointItems pts_items{prep, idx, start, n};
   if (lay.levels == 0) {
-    msm_bucket_kernel<PointItems><<<grid_of(ctx, nb, false), kMsmThreads, 0, st>>>(pts_items, counts, c, K, B0, C);
+    msm_bucket_points_kernel<<<grid_of(ctx, nb, false), kMsmThreads, 0, st>>>(pts_items, counts, c, K, B0, C);
   } else {
-    msm_chunk_scan_kernel<<<K, kScanThreads, 0, st>>>(counts, mA, baseA, c, kChunk0);
-    msm_chunk_kernel<PointItems><<<grid_of(ctx, (int64_t)K * lay.cw[0], false), kMsmThreads, 0, st>>>(
-        pts_items, counts, mA, baseA, c, K, kChunk0, lay.cw[0], PA, C);
-    uint32_t *m_in = mA, *b_in = baseA, *m_out = mB, *b_out = baseB;
-    u32x4 *src = PA, *dst = PB;
-    for (int lv = 1; lv < lay.levels; ++lv) {
-      msm_chunk_scan_kernel<<<K, kScanThreads, 0, st>>>(m_in, m_out, b_out, c, kChunk);
-      msm_chunk_kernel<PartialItems><<<grid_of(ctx, (int64_t)K * lay.cw[lv], false), kMsmThreads, 0, st>>>(
-          PartialItems{src, b_in, lay.cw[lv - 1]}, m_in, m_out, b_out, c, K, kChunk, lay.cw[lv], dst, C);
-      uint32_t* t = m_in;
-      m_in = m_out;
-      m_out = t;
-      t = b_in;
-      b_in = b_out;
-      b_out = t;
-      u32x4* tp = src;
-      src = dst;
-      dst = tp;
+    const int tiles = c > 10 ? 1 << (c - 10) : 1;
+    ChunkLevels CL;
+    CL.levels = lay.levels;
+    for (int lv = 0; lv < lay.levels; ++lv) {
+      uint32_t* m_out = lvl + (size_t)2 * lv * nb;
+      uint32_t* b_out = m_out + nb;
+      u32x4* dst = part + 8 * lay.part_off[lv];
+      const uint32_t* m_in = lv == 0 ? counts : CL.m[lv - 1];
+      const int len = lv == 0 ? kChunk0 : kChunk;
+      msm_tile_sum_kernel<<<(unsigned)(K * tiles), kTileThreads, 0, st>>>(m_in, tsum, c, len, lv > 0);
+      msm_tile_scan_kernel<<<(unsigned)(K * tiles), kTileThreads, 0, st>>>(m_in, tsum, m_out, b_out, c, len, lv > 0);
+      const int grid = grid_of(ctx, (int64_t)K * lay.cw[lv], false);
+      if (lv == 0)
+        msm_chunk_kernel<PointItems><<<grid, kMsmThreads, 0, st>>>(pts_items, m_in, m_out, b_out, c, K, len,
+                                                                    lay.cw[lv], dst, C);
+      else
+        msm_chunk_kernel<PartialItems><<<grid, kMsmThreads, 0, st>>>(
+            PartialItems{CL.part[lv - 1], CL.base[lv - 1], CL.cw[lv - 1]}, m_in, m_out, b_out, c, K, len,
+            lay.cw[lv], dst, C);
+      CL.part[lv] = dst;
+      CL.m[lv] = m_out;
+      CL.base[lv] = b_out;
+      CL.cw[lv] = lay.cw[lv];
     }
-    msm_bucket_kernel<PartialItems><<<grid_of(ctx, nb, false), kMsmThreads, 0, st>>>(
-        PartialItems{src, b_in, lay.cw[lay.levels - 1]}, m_in, c, K, B0, C);
+    msm_bucket_final_kernel<<<grid_of(ctx, nb, false), kMsmThreads, 0, st>>>(CL, c, K, B0, C);
   }
   u32x4 *bi = B0, *wi = W0, *bo = B1, *wo = W1;
   for (int s = c - 1; s >= 0; --s) {
