@@ -335,14 +335,16 @@ MONT_MADS = 162   # 32x32+64-bit multiply-adds of one 9-limb Montgomery product
 
 def msm_products(n, c):
     """Montgomery products of one MSM of n points with c-bit windows: the
-    point preparation (3 per point), the bucket accumulation (9 per added
+    point preparation (4 per point), the bucket accumulation (8 per added
     point), the tree reduction (two additions into W, one addition and one
-    doubling into B per bucket pair and level), and the window merging."""
+    doubling into B per bucket pair and level: 10 + 10 + 10 + 8), and the
+    window merging (c doublings and one addition per window). Products by the
+    curve's small a (16 multiply-adds each) are not counted."""
     K = -(-256 // c)
-    prep = 3 * n
-    accum = 9 * n * K
-    reduce_ = K * ((1 << c) - 1) * (11 + 11 + 11 + 9)
-    merge = K * (9 * c + 11) + 4
+    prep = 4 * n
+    accum = 8 * n * K
+    reduce_ = K * ((1 << c) - 1) * (10 + 10 + 10 + 8)
+    merge = K * (8 * c + 10 + 1) + 4
     return prep + accum + reduce_ + merge
 
 
