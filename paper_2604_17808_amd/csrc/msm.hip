@@ -587,17 +587,24 @@ __device__ FRNTT_INLINE fr_t read_lane(const fr_t& x, int l) {
   return o;
 }
 
-__device__ FRNTT_INLINE fr_t pick(int l, const fr_t& a0, const fr_t& a1, const fr_t& a2, const fr_t& a3) {
+// operand l of up to five, as a masked blend of values (every operand is
+// read, so the selection never becomes a choice of address, which would put
+// the operands in scratch memory)
+__device__ FRNTT_INLINE fr_t pick(int l, const fr_t& a0, const fr_t& a1, const fr_t& a2, const fr_t& a3,
+                                  const fr_t& a4) {
+  const uint32_t m0 = 0u - (uint32_t)(l == 0), m1 = 0u - (uint32_t)(l == 1), m2 = 0u - (uint32_t)(l == 2),
+                 m3 = 0u - (uint32_t)(l == 3), m4 = 0u - (uint32_t)(l == 4);
   fr_t o;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) o.w[i] = l == 0 ? a0.w[i] : l == 1 ? a1.w[i] : l == 2 ? a2.w[i] : a3.w[i];
+  for (int i = 0; i < 8; ++i)
+    o.w[i] = (a0.w[i] & m0) | (a1.w[i] & m1) | (a2.w[i] & m2) | (a3.w[i] & m3) | (a4.w[i] & m4);
   return o;
 }
 
 // X3 = E F, Y3 = G H, Z3 = F G, T3 = E H on lanes 0..3
 __device__ FRNTT_INLINE ept finish_lanes(int lane, const fr_t& E, const fr_t& F, const fr_t& G, const fr_t& H) {
   const int l = lane < 3 ? lane : 3;
-  const fr_t r = mont_mul(pick(l, E, G, F, E), pick(l, F, H, G, H));
+  const fr_t r = mont_mul(pick(l, E, G, F, E, E), pick(l, F, H, G, H, H));
   ept o;
   o.X = read_lane(r, 0);
   o.Y = read_lane(r, 1);
@@ -609,7 +616,7 @@ __device__ FRNTT_INLINE ept finish_lanes(int lane, const fr_t& E, const fr_t& F,
 __device__ FRNTT_INLINE ept dbl_lanes(int lane, const ept& P) {
   const int l = lane < 3 ? lane : 3;
   const fr_t xy = fr_add(P.X, P.Y);
-  const fr_t s = pick(l, P.X, P.Y, P.Z, xy);
+  const fr_t s = pick(l, P.X, P.Y, P.Z, xy, xy);
   const fr_t r = mont_mul(s, s);
   const fr_t A = read_lane(r, 0), B = read_lane(r, 1), Z2 = read_lane(r, 2), S = read_lane(r, 3);
   const fr_t E = fr_sub(fr_sub(S, A), B);
@@ -623,15 +630,8 @@ __device__ FRNTT_INLINE ept dbl_lanes(int lane, const ept& P) {
 // P + Q with d T_Q given
 __device__ FRNTT_INLINE ept add_lanes(int lane, const ept& P, const ept& Q, const fr_t& dTQ) {
   const int l = lane < 4 ? lane : 4;
-  fr_t a, b;
-  if (l == 4) {
-    a = fr_add(P.X, P.Y);
-    b = fr_add(Q.X, Q.Y);
-  } else {
-    a = pick(l, P.X, P.Y, P.T, P.Z);
-    b = pick(l, Q.X, Q.Y, dTQ, Q.Z);
-  }
-  const fr_t r = mont_mul(a, b);
+  const fr_t r = mont_mul(pick(l, P.X, P.Y, P.T, P.Z, fr_add(P.X, P.Y)),
+                          pick(l, Q.X, Q.Y, dTQ, Q.Z, fr_add(Q.X, Q.Y)));
   const fr_t A = read_lane(r, 0), B = read_lane(r, 1), Cc = read_lane(r, 2), D = read_lane(r, 3);
   const fr_t E = fr_sub(fr_sub(read_lane(r, 4), A), B);
   const fr_t F = fr_sub(D, Cc);
