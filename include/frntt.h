@@ -305,6 +305,16 @@ int frntt_rns_field_mont_mul(frntt_rns_field *f, const void *a, const void *b, v
  * EALIGN, ENOMEM, ESTATE (scratch growth during capture), EHIP. */
 int frntt_msm(frntt_ctx *ctx, const void *scalars, const void *points, int64_t n, int window, void *out,
               void *stream);
+/* The same MSM by the paper's dataflow baseline, Presort-PPG (Background,
+ * "Presorting Pippenger"; Table 2): every window's points are first written
+ * to HBM in bucket order (96 bytes per point and window) and the bucket
+ * accumulation reads that copy, where frntt_msm reads the points through the
+ * sorted index lists and never writes a presorted copy (the layout-stationary
+ * dataflow of Alg. 2). Bit-identical result. Needs n K 96 bytes of scratch
+ * more than frntt_msm_workspace_bytes reports. Arguments and errors as
+ * frntt_msm. */
+int frntt_msm_presort(frntt_ctx *ctx, const void *scalars, const void *points, int64_t n, int window, void *out,
+                      void *stream);
 /* Batch scalar multiplication on the same curve: out_i = S_i P_i, affine
  * (16 words per point: x then y, canonical), n points; the layouts, the
  * alignment and the on-curve requirement of frntt_msm. out may not overlap

@@ -265,6 +265,13 @@ struct PointItems {
   const uint32_t* start;  // bucket list starts within the window's list
   int64_t n;
 };
+// The same points already gathered into bucket order (the presorted layout
+// of the Presort-PPG baseline): window k's list at pts + 6 k n.
+struct SortedItems {
+  const u32x4* pts;
+  const uint32_t* start;
+  int64_t n;
+};
 struct PartialItems {
   const u32x4* part;      // window k's partials at part + 8 k CW
   const uint32_t* base;   // bucket partial starts within the window
@@ -284,6 +291,22 @@ __device__ FRNTT_INLINE ept sum_items(const PointItems& S, int64_t g, int64_t k,
   for (uint32_t i = lo + 1; i < hi; ++i) {
     const u32x4* p = S.prep + 6 * (int64_t)list[i];
     acc = add_mixed(acc, load_fr(p), load_fr(p + 2), load_fr(p + 4), C);
+  }
+  return acc;
+}
+
+__device__ FRNTT_INLINE ept sum_items(const SortedItems& S, int64_t g, int64_t k, uint32_t lo, uint32_t hi,
+                                      const MsmConsts& C) {
+  const u32x4* list = S.pts + 6 * (k * S.n + S.start[g]);
+  const u32x4* p0 = list + 6 * (int64_t)lo;
+  ept acc;
+  acc.X = load_fr(p0);
+  acc.Y = load_fr(p0 + 2);
+  acc.Z = C.one;
+  acc.T = mont_mul(acc.X, acc.Y);
+  for (uint32_t i = lo + 1; i < hi; ++i) {
+    const u32x4* q = list + 6 * (int64_t)i;
+    acc = add_mixed(acc, load_fr(q), load_fr(q + 2), load_fr(q + 4), C);
   }
   return acc;
 }
@@ -416,9 +439,23 @@ __global__ __launch_bounds__(kMsmThreads) void msm_chunk_kernel(Items S, const u
   }
 }
 
+// Presort-PPG baseline: every window's points written out in bucket order
+// (96 bytes per (window, point) pair) before the accumulation reads them.
+__global__ __launch_bounds__(kMsmThreads) void msm_gather_kernel(const u32x4* __restrict__ prep,
+                                                                 const uint32_t* __restrict__ idx, int64_t total,
+                                                                 u32x4* __restrict__ sorted) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const u32x4* src = prep + 6 * (int64_t)idx[p];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) sorted[6 * p + i] = src[i];
+  }
+}
+
 // Without chunk levels (n <= kChunk0): B_(k,j) = the sum of bucket j's
 // points, or the zero point for an empty bucket; one bucket per thread.
-__global__ __launch_bounds__(kMsmThreads) void msm_bucket_points_kernel(PointItems S,
+template <class Items>
+__global__ __launch_bounds__(kMsmThreads) void msm_bucket_points_kernel(Items S,
                                                                         const uint32_t* __restrict__ counts, int c,
                                                                         int K, u32x4* __restrict__ B, MsmConsts C) {
   const int64_t total = (int64_t)K << c;
@@ -768,7 +805,7 @@ int chunk_levels(int64_t n, int c, int64_t* cw) {
 }
 
 struct MsmLayout {
-  size_t prep, cnt, lvl, idx, sort, sort_tmp, part, pts, total;
+  size_t prep, cnt, lvl, idx, sort, sort_tmp, part, pts, sorted, total;
   unsigned key_bits;
   int64_t cw[kMaxChunkLevels];
   int64_t part_off[kMaxChunkLevels];  // first partial of each level (points)
@@ -779,8 +816,8 @@ struct MsmLayout {
 // chunk counts and starts of every level; the sorted index lists; the
 // sort's input keys, output keys and input values, and its temporary
 // storage; the partial sums of every level; two (B, W) buffer pairs of
-// K 2^c points.
-MsmLayout msm_layout(int64_t n, int c) {
+// K 2^c points; for the Presort-PPG baseline, the points in bucket order.
+MsmLayout msm_layout(int64_t n, int c, bool presort) {
   MsmLayout L;
   const size_t K = (size_t)windows_for(c), nb = K << c;
   L.levels = chunk_levels(n, c, L.cw);
@@ -804,11 +841,12 @@ MsmLayout msm_layout(int64_t n, int c) {
   L.sort_tmp = up(tmp);
   L.part = up((size_t)off * 128);
   L.pts = up(nb * 128 * 4);
-  L.total = L.prep + L.cnt + L.lvl + L.idx + L.sort + L.sort_tmp + L.part + L.pts;
+  L.sorted = presort ? up(K * (size_t)n * 96) : 0;
+  L.total = L.prep + L.cnt + L.lvl + L.idx + L.sort + L.sort_tmp + L.part + L.pts + L.sorted;
   return L;
 }
 
-size_t msm_workspace_bytes(int64_t n, int c) { return msm_layout(n, c).total; }
+size_t msm_workspace_bytes(int64_t n, int c, bool presort) { return msm_layout(n, c, presort).total; }
 
 int grid_of(const frntt_ctx* ctx, int64_t items, bool capped) {
   int64_t g = (items + kMsmThreads - 1) / kMsmThreads;
@@ -849,11 +887,56 @@ size_t frntt_msm_workspace_bytes(int64_t n, int window) {
   if (n < 0 || n > kMsmMaxPoints) return 0;
   const int c = window ? window : frntt_msm_window(n);
   if (c < 1 || c > kMsmMaxWindow) return 0;
-  return msm_workspace_bytes(n, c);
+  return msm_workspace_bytes(n, c, false);
 }
 
-int frntt_msm(frntt_ctx* ctx, const void* scalars, const void* points, int64_t n, int window, void* out,
-              void* stream) {
+}  // extern "C"
+
+namespace frntt {
+namespace {
+
+// The whole MSM. With presort (the Presort-PPG baseline) every window's
+// points are first written out in bucket order and the accumulation reads
+// that copy; otherwise (LS-PPG) it reads the points through the sorted
+// index lists, and no presorted copy exists.
+template <class Items>
+void launch_accumulation(const frntt_ctx* ctx, const Items& items, const MsmLayout& lay, uint32_t* counts,
+                         uint32_t* tsum, uint32_t* lvl, u32x4* part, int c, int K, u32x4* B0, hipStream_t st,
+                         const MsmConsts& C) {
+  const int64_t nb = (int64_t)K << c;
+  if (lay.levels == 0) {
+    msm_bucket_points_kernel<Items><<<grid_of(ctx, nb, false), kMsmThreads, 0, st>>>(items, counts, c, K, B0, C);
+    return;
+  }
+  const int tiles = c > 10 ? 1 << (c - 10) : 1;
+  ChunkLevels CL;
+  CL.levels = lay.levels;
+  for (int lv = 0; lv < lay.levels; ++lv) {
+    uint32_t* m_out = lvl + (size_t)2 * lv * nb;
+    uint32_t* b_out = m_out + nb;
+    u32x4* dst = part + 8 * lay.part_off[lv];
+    const uint32_t* m_in = lv == 0 ? counts : CL.m[lv - 1];
+    const int len = lv == 0 ? kChunk0 : kChunk;
+    msm_tile_sum_kernel<<<(unsigned)(K * tiles), kTileThreads, 0, st>>>(m_in, tsum, c, len, lv > 0);
+    msm_tile_scan_kernel<<<(unsigned)(K * tiles), kTileThreads, 0, st>>>(m_in, tsum, m_out, b_out, c, len, lv > 0);
+    const int grid = grid_of(ctx, (int64_t)K * lay.cw[lv], false);
+    if (lv == 0)
+      msm_chunk_kernel<Items><<<grid, kMsmThreads, 0, st>>>(items, m_in, m_out, b_out, c, K, len, lay.cw[lv], dst,
+                                                             C);
+    else
+      msm_chunk_kernel<PartialItems><<<grid, kMsmThreads, 0, st>>>(
+          PartialItems{CL.part[lv - 1], CL.base[lv - 1], CL.cw[lv - 1]}, m_in, m_out, b_out, c, K, len,
+          lay.cw[lv], dst, C);
+    CL.part[lv] = dst;
+    CL.m[lv] = m_out;
+    CL.base[lv] = b_out;
+    CL.cw[lv] = lay.cw[lv];
+  }
+  msm_bucket_final_kernel<<<grid_of(ctx, nb, false), kMsmThreads, 0, st>>>(CL, c, K, B0, C);
+}
+
+int msm_run(frntt_ctx* ctx, const void* scalars, const void* points, int64_t n, int window, void* out,
+            void* stream, bool presort) {
   if (!ctx || !out || n < 0 || (n > 0 && (!scalars || !points))) return FRNTT_EINVAL;
   if (n > kMsmMaxPoints || window < 0 || window > kMsmMaxWindow) return FRNTT_ERANGE;
   if ((((uintptr_t)scalars | (uintptr_t)points) & 15) != 0) return FRNTT_EALIGN;
@@ -867,7 +950,7 @@ int frntt_msm(frntt_ctx* ctx, const void* scalars, const void* points, int64_t n
     return msm_status(ctx);
   }
   const int64_t nb = (int64_t)K << c;
-  const MsmLayout lay = msm_layout(n, c);
+  const MsmLayout lay = msm_layout(n, c, presort);
   void* ws = nullptr;
   int rc = get_scratch(ctx, st, lay.total, &ws);
   if (rc != FRNTT_OK) return rc;
@@ -895,6 +978,8 @@ int frntt_msm(frntt_ctx* ctx, const void* scalars, const void* points, int64_t n
   u32x4* W0 = B0 + 8 * nb;
   u32x4* B1 = W0 + 8 * nb;
   u32x4* W1 = B1 + 8 * nb;
+  p += lay.pts;
+  u32x4* sorted = (u32x4*)p;
 
   const int64_t total = (int64_t)K * n;
   zero_words_kernel<<<(unsigned)((2 * nb + 255) / 256), 256, 0, st>>>(start, 2 * nb);
@@ -907,35 +992,11 @@ int frntt_msm(frntt_ctx* ctx, const void* scalars, const void* points, int64_t n
   if (se != hipSuccess) return set_hip_error(ctx, se);
   msm_bounds_kernel<<<grid_of(ctx, total, true), kMsmThreads, 0, st>>>(keys_out, total, start, ends);
   msm_counts_kernel<<<grid_of(ctx, nb, false), kMsmThreads, 0, st>>>(start, ends, counts, n, c, K);
-  const PointItems pts_items{prep, idx, start, n};
-  if (lay.levels == 0) {
-    msm_bucket_points_kernel<<<grid_of(ctx, nb, false), kMsmThreads, 0, st>>>(pts_items, counts, c, K, B0, C);
+  if (presort) {
+    msm_gather_kernel<<<grid_of(ctx, total, false), kMsmThreads, 0, st>>>(prep, idx, total, sorted);
+    launch_accumulation(ctx, SortedItems{sorted, start, n}, lay, counts, tsum, lvl, part, c, K, B0, st, C);
   } else {
-    const int tiles = c > 10 ? 1 << (c - 10) : 1;
-    ChunkLevels CL;
-    CL.levels = lay.levels;
-    for (int lv = 0; lv < lay.levels; ++lv) {
-      uint32_t* m_out = lvl + (size_t)2 * lv * nb;
-      uint32_t* b_out = m_out + nb;
-      u32x4* dst = part + 8 * lay.part_off[lv];
-      const uint32_t* m_in = lv == 0 ? counts : CL.m[lv - 1];
-      const int len = lv == 0 ? kChunk0 : kChunk;
-      msm_tile_sum_kernel<<<(unsigned)(K * tiles), kTileThreads, 0, st>>>(m_in, tsum, c, len, lv > 0);
-      msm_tile_scan_kernel<<<(unsigned)(K * tiles), kTileThreads, 0, st>>>(m_in, tsum, m_out, b_out, c, len, lv > 0);
-      const int grid = grid_of(ctx, (int64_t)K * lay.cw[lv], false);
-      if (lv == 0)
-        msm_chunk_kernel<PointItems><<<grid, kMsmThreads, 0, st>>>(pts_items, m_in, m_out, b_out, c, K, len,
-                                                                    lay.cw[lv], dst, C);
-      else
-        msm_chunk_kernel<PartialItems><<<grid, kMsmThreads, 0, st>>>(
-            PartialItems{CL.part[lv - 1], CL.base[lv - 1], CL.cw[lv - 1]}, m_in, m_out, b_out, c, K, len,
-            lay.cw[lv], dst, C);
-      CL.part[lv] = dst;
-      CL.m[lv] = m_out;
-      CL.base[lv] = b_out;
-      CL.cw[lv] = lay.cw[lv];
-    }
-    msm_bucket_final_kernel<<<grid_of(ctx, nb, false), kMsmThreads, 0, st>>>(CL, c, K, B0, C);
+    launch_accumulation(ctx, PointItems{prep, idx, start, n}, lay, counts, tsum, lvl, part, c, K, B0, st, C);
   }
   u32x4 *bi = B0, *wi = W0, *bo = B1, *wo = W1;
   for (int s = c - 1; s >= 0; --s) {
@@ -950,6 +1011,21 @@ int frntt_msm(frntt_ctx* ctx, const void* scalars, const void* points, int64_t n
   }
   msm_merge_kernel<<<1, 64, 0, st>>>(wi, c, K, (uint32_t*)out, C);
   return msm_status(ctx);
+}
+
+}  // namespace
+}  // namespace frntt
+
+extern "C" {
+
+int frntt_msm(frntt_ctx* ctx, const void* scalars, const void* points, int64_t n, int window, void* out,
+              void* stream) {
+  return msm_run(ctx, scalars, points, n, window, out, stream, false);
+}
+
+int frntt_msm_presort(frntt_ctx* ctx, const void* scalars, const void* points, int64_t n, int window, void* out,
+                      void* stream) {
+  return msm_run(ctx, scalars, points, n, window, out, stream, true);
 }
 
 int frntt_ec_mul(frntt_ctx* ctx, const void* scalars, const void* points, int64_t n, void* out, void* stream) {

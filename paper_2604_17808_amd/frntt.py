@@ -86,6 +86,7 @@ SIGNATURES = {
     "frntt_rns_field_decode": (_i, [_vp, _vp, _vp, ctypes.c_int64, _vp]),
     "frntt_rns_field_mont_mul": (_i, [_vp, _vp, _vp, _vp, ctypes.c_int64, _vp]),
     "frntt_msm": (_i, [_vp, _vp, _vp, ctypes.c_int64, _i, _vp, _vp]),
+    "frntt_msm_presort": (_i, [_vp, _vp, _vp, ctypes.c_int64, _i, _vp, _vp]),
     "frntt_msm_window": (_i, [ctypes.c_int64]),
     "frntt_ec_mul": (_i, [_vp, _vp, _vp, ctypes.c_int64, _vp, _vp]),
     "frntt_msm_workspace_bytes": (_sz, [ctypes.c_int64, _i]),
@@ -279,6 +280,11 @@ class Context:
     # scalars n x 8 words, points n x 16 words (x, y), out 16 words (x, y)
     def msm(self, scalars: int, points: int, n: int, out: int, window: int = 0, stream: int = 0):
         return _check(lib().frntt_msm(self._h, scalars, points, n, window, out, stream), "frntt_msm")
+
+    def msm_presort(self, scalars: int, points: int, n: int, out: int, window: int = 0, stream: int = 0):
+        """The Presort-PPG baseline of the same MSM (bit-identical)."""
+        return _check(lib().frntt_msm_presort(self._h, scalars, points, n, window, out, stream),
+                      "frntt_msm_presort")
 
     def ec_mul(self, scalars: int, points: int, n: int, out: int, stream: int = 0):
         return _check(lib().frntt_ec_mul(self._h, scalars, points, n, out, stream), "frntt_ec_mul")

@@ -1,5 +1,6 @@
-"""Parity of the multi-scalar multiplication (Alg. 2, LS-PPG) and the batch
-scalar multiplication with the oracle, bit-exact: the result is an affine
+"""Parity of the multi-scalar multiplication (Alg. 2, LS-PPG, and its
+Presort-PPG baseline) and the batch scalar multiplication with the oracle,
+bit-exact: the result is an affine
 point in canonical form, which is unique, so the HIP output must equal the
 oracle's word for word.
 
@@ -77,13 +78,18 @@ def _host_points(t):
 
 
 def _msm(ctx, scalars, points, window=0):
+    """LS-PPG result, after checking that the Presort-PPG baseline agrees."""
     n = len(scalars)
     sc = _dev_words(scalars) if n else torch.zeros((1, 8), dtype=torch.int32, device="cuda")
     pt = _dev_points(points) if n else torch.zeros((1, 16), dtype=torch.int32, device="cuda")
     out = torch.empty(16, dtype=torch.int32, device="cuda")
+    base = torch.empty(16, dtype=torch.int32, device="cuda")
     ctx.msm(sc.data_ptr(), pt.data_ptr(), n, out.data_ptr(), window)
+    ctx.msm_presort(sc.data_ptr(), pt.data_ptr(), n, base.data_ptr(), window)
     torch.cuda.synchronize()
-    return _host_point(out)
+    got = _host_point(out)
+    assert _host_point(base) == got, "Presort-PPG and LS-PPG differ"
+    return got
 
 
 def _rand_points(n, seed):
@@ -229,10 +235,13 @@ def test_msm_full_size_generator_multiples(ctx):
     for j in range(4):
         assert got[j] == M.mul(kk[j], BASE8)
     out = torch.empty(16, dtype=torch.int32, device="cuda")
+    base = torch.empty(16, dtype=torch.int32, device="cuda")
     ctx.msm(s_t.data_ptr(), pts.data_ptr(), n, out.data_ptr())
+    ctx.msm_presort(s_t.data_ptr(), pts.data_ptr(), n, base.data_ptr())
     torch.cuda.synchronize()
     total = sum(a * b for a, b in zip(si.to_ints(s), si.to_ints(k))) % L_ORDER
     assert _host_point(out) == M.mul(total, BASE8)
+    assert _host_point(base) == _host_point(out)
 
 
 def test_msm_argument_errors(ctx):
@@ -248,6 +257,8 @@ def test_msm_argument_errors(ctx):
     assert L.frntt_msm(ctx._h, p, p, 1, -1, o.data_ptr(), None) == B.ERANGE
     assert L.frntt_msm(ctx._h, p, p, (1 << 28) + 1, 0, o.data_ptr(), None) == B.ERANGE
     assert L.frntt_msm(ctx._h, p + 4, p, 1, 0, o.data_ptr(), None) == B.EALIGN
+    assert L.frntt_msm_presort(ctx._h, p, p + 4, 1, 0, o.data_ptr(), None) == B.EALIGN
+    assert L.frntt_msm_presort(ctx._h, p, p, 1, 21, o.data_ptr(), None) == B.ERANGE
     assert L.frntt_ec_mul(ctx._h, p, p + 4, 1, o.data_ptr(), None) == B.EALIGN
     assert L.frntt_ec_mul(ctx._h, p, p, -1, o.data_ptr(), None) == B.EINVAL
     assert L.frntt_ec_mul(ctx._h, p, p, 0, o.data_ptr(), None) == B.OK
