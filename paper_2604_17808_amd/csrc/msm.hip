@@ -4,11 +4,14 @@
 // Merging, each a launch (the reduction one launch per tree level).
 //
 // The curve is a x^2 + y^2 = 1 + d x^2 y^2 over Fr (BN254's scalar field),
-// a = 168700, d = 168696 (Baby Jubjub). a is a square and d is not, so the
-// unified addition law in extended coordinates (X : Y : Z : T), x = X/Z,
-// y = Y/Z, T Z = X Y, has no exceptional cases (zero point (0 : 1 : 1 : 0),
-// as in the paper). Coordinates are kept in Montgomery form (R = 2^261) and
-// multiplied with the library's 29-bit-limb Montgomery product.
+// a = 168700, d = 168696 (Baby Jubjub). Inside, points live on the
+// isomorphic curve -x'^2 + y^2 = 1 + d' x'^2 y^2 with x' = s x, s^2 = -a,
+// d' = -d / a (-1 and a are squares mod r, so s exists; d' is a non-square
+// like d), where the extended-coordinate formulas of Hisil, Wong, Carter and
+// Dawson (2008) for a = -1 are cheapest and complete: (X : Y : Z : T),
+// x' = X/Z, y = Y/Z, T Z = X Y, zero point (0 : 1 : 1 : 0) as in the paper.
+// Coordinates are kept in Montgomery form (R = 2^261) and multiplied with the
+// library's 29-bit-limb Montgomery product.
 //
 // Bucketize is a counting sort per window (histogram, exclusive scan, then
 // scatter of point indices), which is the argsort of the paper's step; the
@@ -33,10 +36,11 @@ constexpr int kScanThreads = 1024;
 constexpr uint32_t kCurveA = 168700, kCurveD = 168696;
 
 struct MsmConsts {
-  fr_t r2;   // 2^522 mod r (into Montgomery form)
-  fr_t one;  // 2^261 mod r
-  fr_t a;    // a 2^261 mod r
-  fr_t d;    // d 2^261 mod r
+  fr_t r2;    // 2^522 mod r (into Montgomery form)
+  fr_t one;   // 2^261 mod r
+  fr_t s;     // s = sqrt(-a), Montgomery form
+  fr_t sinv;  // s^-1, Montgomery form
+  fr_t k;     // 2 d' = -2 d / a, Montgomery form
 };
 
 // extended coordinates, Montgomery form
@@ -82,46 +86,29 @@ __device__ FRNTT_INLINE ept ept_zero(const MsmConsts& C) {
   return e;
 }
 
-// a x mod r for canonical x and the curve's small a (a < 2^18): the 9-word
-// product v, a quotient estimate q = floor(top 64 bits of v / (r_7 + 1))
-// (never above floor(v / r), and below it by at most one since r_7 is above
-// 2^29), then v - q r < 2r and one conditional subtraction. Montgomery form
-// is kept: a (x 2^261) = (a x) 2^261.
-__device__ FRNTT_INLINE fr_t fr_mul_small(const fr_t& x, uint32_t a) {
-  uint32_t v[9];
-  uint64_t cy = 0;
+// x / 2 mod r for canonical x: x / 2, or (x + r) / 2 for odd x (x + r < 2^255)
+__device__ FRNTT_INLINE fr_t fr_half(const fr_t& a) {
+  fr_t x = a;
+  if (x.w[0] & 1u) {
+    uint32_t cy = 0;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const uint64_t t = (uint64_t)x.w[i] * a + cy;
-    v[i] = (uint32_t)t;
-    cy = t >> 32;
+    for (int i = 0; i < 8; ++i) x.w[i] = addc(x.w[i], fr_mod_word(i), cy, &cy);
   }
-  v[8] = (uint32_t)cy;
-  const uint64_t top = ((uint64_t)v[8] << 32) | v[7];
-  const uint32_t q = (uint32_t)(top / ((uint64_t)FR_R7 + 1));
-  fr_t o;
-  uint64_t mc = 0;
-  uint32_t br = 0;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const uint64_t t = (uint64_t)fr_mod_word(i) * q + mc;
-    mc = t >> 32;
-    o.w[i] = subb(v[i], (uint32_t)t, br, &br);
-  }
-  return fr_reduce_once(o);
+  for (int i = 0; i < 7; ++i) x.w[i] = (x.w[i] >> 1) | (x.w[i + 1] << 31);
+  x.w[7] >>= 1;
+  return x;
 }
 
-// P + (x2, y2) for an affine point given as x2, y2 and d x2 y2 (Montgomery
-// form): the unified addition with Z2 = 1 (8 products and one by a).
-__device__ FRNTT_INLINE ept add_mixed(const ept& P, const fr_t& x2, const fr_t& y2, const fr_t& dt2,
+// P + Q for Q = (x2', y2) affine, given as y2 - x2', y2 + x2' and 2 d' x2' y2
+// (the mixed addition with Z2 = 1: 7 products).
+__device__ FRNTT_INLINE ept add_mixed(const ept& P, const fr_t& ymx2, const fr_t& ypx2, const fr_t& kt2,
                                       const MsmConsts& C) {
-  const fr_t A = mont_mul(P.X, x2);
-  const fr_t B = mont_mul(P.Y, y2);
-  const fr_t Cc = mont_mul(P.T, dt2);
-  const fr_t E = fr_sub(fr_sub(mont_mul(fr_add(P.X, P.Y), fr_add(x2, y2)), A), B);
-  const fr_t F = fr_sub(P.Z, Cc);
-  const fr_t G = fr_add(P.Z, Cc);
-  const fr_t H = fr_sub(B, fr_mul_small(A, kCurveA));
+  const fr_t A = mont_mul(fr_sub(P.Y, P.X), ymx2);
+  const fr_t B = mont_mul(fr_add(P.Y, P.X), ypx2);
+  const fr_t Cc = mont_mul(P.T, kt2);
+  const fr_t D = fr_add(P.Z, P.Z);
+  const fr_t E = fr_sub(B, A), F = fr_sub(D, Cc), G = fr_add(D, Cc), H = fr_add(B, A);
   ept o;
   o.X = mont_mul(E, F);
   o.Y = mont_mul(G, H);
@@ -130,16 +117,14 @@ __device__ FRNTT_INLINE ept add_mixed(const ept& P, const fr_t& x2, const fr_t& 
   return o;
 }
 
-// P + Q, the unified addition (10 products).
+// P + Q, the unified addition (9 products).
 __device__ FRNTT_INLINE ept add_full(const ept& P, const ept& Q, const MsmConsts& C) {
-  const fr_t A = mont_mul(P.X, Q.X);
-  const fr_t B = mont_mul(P.Y, Q.Y);
-  const fr_t Cc = mont_mul(mont_mul(P.T, Q.T), C.d);
-  const fr_t D = mont_mul(P.Z, Q.Z);
-  const fr_t E = fr_sub(fr_sub(mont_mul(fr_add(P.X, P.Y), fr_add(Q.X, Q.Y)), A), B);
-  const fr_t F = fr_sub(D, Cc);
-  const fr_t G = fr_add(D, Cc);
-  const fr_t H = fr_sub(B, fr_mul_small(A, kCurveA));
+  const fr_t A = mont_mul(fr_sub(P.Y, P.X), fr_sub(Q.Y, Q.X));
+  const fr_t B = mont_mul(fr_add(P.Y, P.X), fr_add(Q.Y, Q.X));
+  const fr_t Cc = mont_mul(mont_mul(P.T, Q.T), C.k);
+  const fr_t ZZ = mont_mul(P.Z, Q.Z);
+  const fr_t D = fr_add(ZZ, ZZ);
+  const fr_t E = fr_sub(B, A), F = fr_sub(D, Cc), G = fr_add(D, Cc), H = fr_add(B, A);
   ept o;
   o.X = mont_mul(E, F);
   o.Y = mont_mul(G, H);
@@ -148,26 +133,55 @@ __device__ FRNTT_INLINE ept add_full(const ept& P, const ept& Q, const MsmConsts
   return o;
 }
 
-// 2 P, the doubling formula derived from the unified addition (it uses
-// neither T nor d; 8 products and one by a): with A = X^2, B = Y^2, G = a A + B, the
-// affine result is (2 x y / G, (B - a A) / (2 - G)) scaled by Z^2.
+// 2 P (8 products; uses neither T nor d'): with A = X^2, B = Y^2 and the
+// curve's -1, the affine result is (2 x' y / (B - A), (-A - B) / (B - A - 2))
+// scaled by Z^2.
 __device__ FRNTT_INLINE ept dbl(const ept& P, const MsmConsts& C) {
   const fr_t A = mont_mul(P.X, P.X);
   const fr_t B = mont_mul(P.Y, P.Y);
   const fr_t Z2 = mont_mul(P.Z, P.Z);
-  const fr_t Cc = fr_add(Z2, Z2);
   const fr_t XY = fr_add(P.X, P.Y);
   const fr_t E = fr_sub(fr_sub(mont_mul(XY, XY), A), B);
-  const fr_t Da = fr_mul_small(A, kCurveA);
-  const fr_t G = fr_add(Da, B);
-  const fr_t F = fr_sub(G, Cc);
-  const fr_t H = fr_sub(Da, B);
+  const fr_t G = fr_sub(B, A);
+  const fr_t F = fr_sub(G, fr_add(Z2, Z2));
+  const fr_t H = fr_sub(fr_zero(), fr_add(A, B));
   ept o;
   o.X = mont_mul(E, F);
   o.Y = mont_mul(G, H);
   o.Z = mont_mul(F, G);
   o.T = mont_mul(E, H);
   return o;
+}
+
+// The extended point of a prepared one: x' = ((y + x') - (y - x')) / 2,
+// y = ((y + x') + (y - x')) / 2, Z = 1, T = x' y (one product).
+__device__ FRNTT_INLINE ept from_prepared(const fr_t& ymx, const fr_t& ypx, const MsmConsts& C) {
+  ept e;
+  e.X = fr_half(fr_sub(ypx, ymx));
+  e.Y = fr_half(fr_add(ypx, ymx));
+  e.Z = C.one;
+  e.T = mont_mul(e.X, e.Y);
+  return e;
+}
+
+// Prepared form of an affine input point (x, y): y - x', y + x', 2 d' x' y
+// in Montgomery form (x' = s x).
+__device__ FRNTT_INLINE void prepare_point(const u32x4* in, fr_t* ymx, fr_t* ypx, fr_t* kt, const MsmConsts& C) {
+  const fr_t xp = mont_mul(mont_mul(load_fr(in), C.r2), C.s);
+  const fr_t ym = mont_mul(load_fr(in + 2), C.r2);
+  *ymx = fr_sub(ym, xp);
+  *ypx = fr_add(ym, xp);
+  *kt = mont_mul(mont_mul(xp, ym), C.k);
+}
+
+// Affine (x, y) = (X / (s Z), Y / Z) in canonical form
+__device__ fr_t fr_inverse(const fr_t& a);
+__device__ FRNTT_INLINE void to_affine(const ept& P, const MsmConsts& C, fr_t* x, fr_t* y) {
+  fr_t one_c = fr_zero();
+  one_c.w[0] = 1;
+  const fr_t zi = fr_inverse(mont_mul(P.Z, one_c));
+  *x = mont_mul(mont_mul(P.X, zi), C.sinv);
+  *y = mont_mul(P.Y, zi);
 }
 
 // c-bit digit k of a 256-bit scalar (zero beyond bit 255)
@@ -192,7 +206,7 @@ __device__ FRNTT_INLINE void load_scalar(const u32x4* p, uint32_t* s) {
 // sort); window k's entries then fill positions [k n, (k + 1) n) in digit
 // order, and the bucket bounds are the runs of equal keys.
 
-// Points into Montgomery form with d x y beside them (96 bytes per point),
+// Points into their prepared form (96 bytes per point),
 // and the sort's input pairs: key k 2^c + digit at k n + i, value i.
 __global__ __launch_bounds__(kMsmThreads) void msm_prep_kernel(const u32x4* __restrict__ pts,
                                                                const u32x4* __restrict__ sc, int64_t n, int c,
@@ -200,12 +214,11 @@ __global__ __launch_bounds__(kMsmThreads) void msm_prep_kernel(const u32x4* __re
                                                                uint32_t* __restrict__ keys,
                                                                uint32_t* __restrict__ vals, MsmConsts C) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const fr_t xm = mont_mul(load_fr(pts + 4 * i), C.r2);
-    const fr_t ym = mont_mul(load_fr(pts + 4 * i + 2), C.r2);
-    const fr_t dt = mont_mul(mont_mul(xm, ym), C.d);
-    store_fr(prep + 6 * i, xm);
-    store_fr(prep + 6 * i + 2, ym);
-    store_fr(prep + 6 * i + 4, dt);
+    fr_t ymx, ypx, kt;
+    prepare_point(pts + 4 * i, &ymx, &ypx, &kt, C);
+    store_fr(prep + 6 * i, ymx);
+    store_fr(prep + 6 * i + 2, ypx);
+    store_fr(prep + 6 * i + 4, kt);
     uint32_t s[8];
     load_scalar(sc + 2 * i, s);
     for (int k = 0; k < K; ++k) {
@@ -257,7 +270,7 @@ __global__ __launch_bounds__(kMsmThreads) void msm_counts_kernel(uint32_t* __res
 
 constexpr int kChunk0 = 32, kChunk = 32;
 
-// Item i of bucket j's list: a point (x, y, d x y from the prepared array,
+// Item i of bucket j's list: a point (its prepared form,
 // reached through the index list) or a partial sum.
 struct PointItems {
   const u32x4* prep;
@@ -283,11 +296,7 @@ __device__ FRNTT_INLINE ept sum_items(const PointItems& S, int64_t g, int64_t k,
                                       const MsmConsts& C) {
   const uint32_t* list = S.idx + k * S.n + S.start[g];
   const u32x4* p0 = S.prep + 6 * (int64_t)list[lo];
-  ept acc;
-  acc.X = load_fr(p0);
-  acc.Y = load_fr(p0 + 2);
-  acc.Z = C.one;
-  acc.T = mont_mul(acc.X, acc.Y);
+  ept acc = from_prepared(load_fr(p0), load_fr(p0 + 2), C);
   for (uint32_t i = lo + 1; i < hi; ++i) {
     const u32x4* p = S.prep + 6 * (int64_t)list[i];
     acc = add_mixed(acc, load_fr(p), load_fr(p + 2), load_fr(p + 4), C);
@@ -299,11 +308,7 @@ __device__ FRNTT_INLINE ept sum_items(const SortedItems& S, int64_t g, int64_t k
                                       const MsmConsts& C) {
   const u32x4* list = S.pts + 6 * (k * S.n + S.start[g]);
   const u32x4* p0 = list + 6 * (int64_t)lo;
-  ept acc;
-  acc.X = load_fr(p0);
-  acc.Y = load_fr(p0 + 2);
-  acc.Z = C.one;
-  acc.T = mont_mul(acc.X, acc.Y);
+  ept acc = from_prepared(load_fr(p0), load_fr(p0 + 2), C);
   for (uint32_t i = lo + 1; i < hi; ++i) {
     const u32x4* q = list + 6 * (int64_t)i;
     acc = add_mixed(acc, load_fr(q), load_fr(q + 2), load_fr(q + 4), C);
@@ -657,30 +662,28 @@ __device__ FRNTT_INLINE ept dbl_lanes(int lane, const ept& P) {
   const fr_t r = mont_mul(s, s);
   const fr_t A = read_lane(r, 0), B = read_lane(r, 1), Z2 = read_lane(r, 2), S = read_lane(r, 3);
   const fr_t E = fr_sub(fr_sub(S, A), B);
-  const fr_t Da = fr_mul_small(A, kCurveA);
-  const fr_t G = fr_add(Da, B);
+  const fr_t G = fr_sub(B, A);
   const fr_t F = fr_sub(G, fr_add(Z2, Z2));
-  const fr_t H = fr_sub(Da, B);
+  const fr_t H = fr_sub(fr_zero(), fr_add(A, B));
   return finish_lanes(lane, E, F, G, H);
 }
 
-// P + Q with d T_Q given
-__device__ FRNTT_INLINE ept add_lanes(int lane, const ept& P, const ept& Q, const fr_t& dTQ) {
-  const int l = lane < 4 ? lane : 4;
-  const fr_t r = mont_mul(pick(l, P.X, P.Y, P.T, P.Z, fr_add(P.X, P.Y)),
-                          pick(l, Q.X, Q.Y, dTQ, Q.Z, fr_add(Q.X, Q.Y)));
-  const fr_t A = read_lane(r, 0), B = read_lane(r, 1), Cc = read_lane(r, 2), D = read_lane(r, 3);
-  const fr_t E = fr_sub(fr_sub(read_lane(r, 4), A), B);
-  const fr_t F = fr_sub(D, Cc);
-  const fr_t G = fr_add(D, Cc);
-  const fr_t H = fr_sub(B, fr_mul_small(A, kCurveA));
+// P + Q with 2 d' T_Q given
+__device__ FRNTT_INLINE ept add_lanes(int lane, const ept& P, const ept& Q, const fr_t& kTQ) {
+  const int l = lane < 3 ? lane : 3;
+  const fr_t ymx = fr_sub(P.Y, P.X), ypx = fr_add(P.Y, P.X);
+  const fr_t r = mont_mul(pick(l, ymx, ypx, P.T, P.Z, P.Z),
+                          pick(l, fr_sub(Q.Y, Q.X), fr_add(Q.Y, Q.X), kTQ, Q.Z, Q.Z));
+  const fr_t A = read_lane(r, 0), B = read_lane(r, 1), Cc = read_lane(r, 2), ZZ = read_lane(r, 3);
+  const fr_t D = fr_add(ZZ, ZZ);
+  const fr_t E = fr_sub(B, A), F = fr_sub(D, Cc), G = fr_add(D, Cc), H = fr_add(B, A);
   return finish_lanes(lane, E, F, G, H);
 }
 
 constexpr int kMergeMaxK = 256;
 
 // MSM = sum_k 2^(c k) W_k from the top window down (one wave; the W_k and
-// their d T are staged in LDS first), then (x, y) = (X/Z, Y/Z) in canonical
+// their 2 d' T are staged in LDS first), then the affine (x, y) in canonical
 // form: out[0..7] = x, out[8..15] = y.
 __global__ __launch_bounds__(64) void msm_merge_kernel(const u32x4* __restrict__ W, int c, int K,
                                                        uint32_t* __restrict__ out, MsmConsts C) {
@@ -692,7 +695,7 @@ __global__ __launch_bounds__(64) void msm_merge_kernel(const u32x4* __restrict__
     sw[k][1] = w.Y;
     sw[k][2] = w.Z;
     sw[k][3] = w.T;
-    sw[k][4] = mont_mul(w.T, C.d);
+    sw[k][4] = mont_mul(w.T, C.k);
   }
   __syncthreads();
   ept acc = ept_zero(C);
@@ -706,10 +709,8 @@ __global__ __launch_bounds__(64) void msm_merge_kernel(const u32x4* __restrict__
     w.T = sw[k][3];
     acc = add_lanes(lane, acc, w, sw[k][4]);
   }
-  fr_t one_c = fr_zero();
-  one_c.w[0] = 1;
-  const fr_t zi = fr_inverse(mont_mul(acc.Z, one_c));
-  const fr_t x = mont_mul(acc.X, zi), y = mont_mul(acc.Y, zi);
+  fr_t x, y;
+  to_affine(acc, C, &x, &y);
   if (lane == 0) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -727,21 +728,19 @@ __global__ __launch_bounds__(kMsmThreads) void ec_mul_kernel(const u32x4* __rest
                                                              const u32x4* __restrict__ pts, int64_t n,
                                                              u32x4* __restrict__ out, MsmConsts C) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const fr_t xm = mont_mul(load_fr(pts + 4 * i), C.r2);
-    const fr_t ym = mont_mul(load_fr(pts + 4 * i + 2), C.r2);
-    const fr_t dt = mont_mul(mont_mul(xm, ym), C.d);
+    fr_t ymx, ypx, kt;
+    prepare_point(pts + 4 * i, &ymx, &ypx, &kt, C);
     uint32_t s[8];
     load_scalar(sc + 2 * i, s);
     ept acc = ept_zero(C);
     for (int b = 255; b >= 0; --b) {
       acc = dbl(acc, C);
-      if ((s[b >> 5] >> (b & 31)) & 1u) acc = add_mixed(acc, xm, ym, dt, C);
+      if ((s[b >> 5] >> (b & 31)) & 1u) acc = add_mixed(acc, ymx, ypx, kt, C);
     }
-    fr_t one_c = fr_zero();
-    one_c.w[0] = 1;
-    const fr_t zi = fr_inverse(mont_mul(acc.Z, one_c));
-    store_fr(out + 4 * i, mont_mul(acc.X, zi));
-    store_fr(out + 4 * i + 2, mont_mul(acc.Y, zi));
+    fr_t x, y;
+    to_affine(acc, C, &x, &y);
+    store_fr(out + 4 * i, x);
+    store_fr(out + 4 * i + 2, y);
   }
 }
 
@@ -760,12 +759,57 @@ host::Fe times_pow2(host::Fe x, int k) {
   return x;
 }
 
+bool fe_eq(const host::Fe& a, const host::Fe& b) {
+  return a.v[0] == b.v[0] && a.v[1] == b.v[1] && a.v[2] == b.v[2] && a.v[3] == b.v[3];
+}
+
+// A square root of a quadratic residue a mod r by Tonelli and Shanks
+// (r - 1 = 2^28 q with q odd; 5 generates Fr^*, so it is a non-residue).
+host::Fe fe_sqrt(const host::Field& F, const host::Fe& a) {
+  host::Fe q = host::kR;
+  q.v[0] -= 1;
+  int S = 0;
+  while ((q.v[0] & 1) == 0) {
+    for (int i = 0; i < 4; ++i) q.v[i] = (q.v[i] >> 1) | (i < 3 ? (q.v[i + 1] << 63) : 0);
+    ++S;
+  }
+  host::Fe q1 = q;  // (q + 1) / 2
+  host::add_in(q1, host::from_u64(1));
+  for (int i = 0; i < 4; ++i) q1.v[i] = (q1.v[i] >> 1) | (i < 3 ? (q1.v[i + 1] << 63) : 0);
+  const host::Fe one = host::from_u64(1);
+  host::Fe c = F.pow(host::from_u64(5), q), t = F.pow(a, q), x = F.pow(a, q1);
+  int m = S;
+  while (!fe_eq(t, one)) {
+    int i = 0;
+    host::Fe t2 = t;
+    while (!fe_eq(t2, one) && i < m) {
+      t2 = F.mul(t2, t2);
+      ++i;
+    }
+    if (i >= m) break;  // not a residue (cannot happen for -a)
+    host::Fe b = c;
+    for (int j = 0; j < m - i - 1; ++j) b = F.mul(b, b);
+    m = i;
+    c = F.mul(b, b);
+    t = F.mul(t, c);
+    x = F.mul(x, b);
+  }
+  return x;
+}
+
 MsmConsts make_consts() {
+  const host::Field F;
   MsmConsts C;
   fe_words(times_pow2(host::from_u64(1), 522), &C.r2);
   fe_words(times_pow2(host::from_u64(1), 261), &C.one);
-  fe_words(times_pow2(host::from_u64(kCurveA), 261), &C.a);
-  fe_words(times_pow2(host::from_u64(kCurveD), 261), &C.d);
+  const host::Fe a = host::from_u64(kCurveA), d = host::from_u64(kCurveD);
+  const host::Fe s = fe_sqrt(F, host::sub(host::from_u64(0), a));
+  const host::Fe sinv = F.inv(s);
+  // 2 d' = -2 d / a
+  const host::Fe k = host::sub(host::from_u64(0), F.mul(host::add(d, d), F.inv(a)));
+  fe_words(times_pow2(s, 261), &C.s);
+  fe_words(times_pow2(sinv, 261), &C.sinv);
+  fe_words(times_pow2(k, 261), &C.k);
   return C;
 }
 
