@@ -300,9 +300,11 @@ int frntt_rns_field_mont_mul(frntt_rns_field *f, const void *a, const void *b, v
  *   window:  c in [1, 20], or 0 for frntt_msm_window(n).
  * n = 0 gives the zero point. The work is queued on `stream` (0: the null
  * stream) in the context's per-stream scratch (frntt_msm_workspace_bytes;
- * grown as needed, so not inside a graph capture the first time). Errors:
- * EINVAL (null pointer, n < 0), ERANGE (n > 2^26, window outside [0, 20]),
- * EALIGN, ENOMEM, ESTATE (scratch growth during capture), EHIP. */
+ * grown as needed, with a synchronisation of the stream when it grows). An
+ * MSM cannot be captured into a hipGraph (its radix sort clears counters
+ * with memset nodes): under a stream capture the call returns ESTATE and
+ * enqueues nothing. Errors: EINVAL (null pointer, n < 0), ERANGE (n > 2^26,
+ * window outside [0, 20]), EALIGN, ENOMEM, ESTATE (stream capture), EHIP. */
 int frntt_msm(frntt_ctx *ctx, const void *scalars, const void *points, int64_t n, int window, void *out,
               void *stream);
 /* The same MSM by the paper's dataflow baseline, Presort-PPG (Background,

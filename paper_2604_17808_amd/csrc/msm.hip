@@ -987,6 +987,9 @@ int msm_run(frntt_ctx* ctx, const void* scalars, const void* points, int64_t n, 
   const int c = window ? window : frntt_msm_window(n);
   const int K = n ? windows_for(c) : 0;
   const hipStream_t st = (hipStream_t)stream;
+  // the radix sort clears its counters with memset nodes, which graph
+  // replays do not redo reliably: an MSM is never captured
+  if (stream_capturing(st)) return FRNTT_ESTATE;
   MsmDeviceGuard guard(ctx->device);
   static const MsmConsts C = make_consts();
   if (n == 0) {

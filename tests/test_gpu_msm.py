@@ -263,3 +263,28 @@ def test_msm_argument_errors(ctx):
     assert L.frntt_ec_mul(ctx._h, p, p, -1, o.data_ptr(), None) == B.EINVAL
     assert L.frntt_ec_mul(ctx._h, p, p, 0, o.data_ptr(), None) == B.OK
     assert fr.msm_workspace_bytes(-1) == 0 and fr.msm_workspace_bytes(10, 21) == 0
+
+
+def test_msm_refuses_stream_capture(ctx):
+    # an MSM is never captured into a graph (its sort clears counters with
+    # memset nodes): under a capture the call returns ESTATE, enqueues
+    # nothing, and the stream works as before afterwards
+    pts = _rand_points(3, 1100)
+    sc = _scalars(3, 1101)
+    s_t, p_t = _dev_words(sc), _dev_points(pts)
+    out = torch.full((16,), 7, dtype=torch.int32, device="cuda")
+    st = torch.cuda.Stream()
+    L = fr.lib()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(st):
+        with torch.cuda.graph(g, stream=st):
+            rc = L.frntt_msm(ctx._h, s_t.data_ptr(), p_t.data_ptr(), 3, 0, out.data_ptr(), st.cuda_stream)
+            rcb = L.frntt_msm_presort(ctx._h, s_t.data_ptr(), p_t.data_ptr(), 3, 0, out.data_ptr(),
+                                      st.cuda_stream)
+    assert rc == B.ESTATE and rcb == B.ESTATE
+    torch.cuda.synchronize()
+    assert bool((out == 7).all())
+    with torch.cuda.stream(st):
+        ctx.msm(s_t.data_ptr(), p_t.data_ptr(), 3, out.data_ptr(), 0, st.cuda_stream)
+    torch.cuda.synchronize()
+    assert _host_point(out) == M.msm_naive(sc, pts)
