@@ -7,7 +7,7 @@ oracle's word for word.
 Cases: small inputs against the plain sum of products for window widths
 1..20 (one window, many windows, a ragged top window) and the edge scalars
 (0, 1, r - 1, 2^256 - 1, the subgroup order, equal points, a point and its
-negative); medium and ragged sizes with walk-generated points, whose sum has
+negative, the points of order 1, 2 and 4); medium and ragged sizes with walk-generated points, whose sum has
 a closed form by linearity; and the full 2^22-point configuration with points
 k_i G produced by the batch scalar multiplication, where the result must be
 ((sum_i S_i k_i) mod l) G. The oracle (oracle/msm.py) is pinned in
@@ -288,3 +288,36 @@ def test_msm_refuses_stream_capture(ctx):
         ctx.msm(s_t.data_ptr(), p_t.data_ptr(), 3, out.data_ptr(), 0, st.cuda_stream)
     torch.cuda.synchronize()
     assert _host_point(out) == M.msm_naive(sc, pts)
+
+
+def _small_order_points():
+    """The zero point (0, 1), the point of order 2 (0, -1) and the two
+    points of order 4 (+-1/sqrt(a), 0)."""
+    u = pow(M.sqrt_mod(M.A), -1, M.R)
+    pts = [(0, 1), (0, M.R - 1), (u, 0), (M.R - u, 0)]
+    assert all(M.on_curve(p) for p in pts)
+    return pts
+
+
+def test_msm_small_order_points(ctx):
+    tors = _small_order_points()
+    rnd = _rand_points(4, 1200)
+    pts = tors + rnd + tors
+    sc = [5, 7, 9, 11] + _scalars(4, 1201) + [(1 << 256) - 1, 2, 3, 1]
+    for window in (0, 2, 5, 16):
+        assert _msm(ctx, sc, pts, window) == M.msm_naive(sc, pts)
+    # only small-order points: the sum is a small-order point too
+    assert _msm(ctx, [3, 1, 1, 2], tors) == M.msm_naive([3, 1, 1, 2], tors)
+
+
+def test_ec_mul_small_order_points(ctx):
+    tors = _small_order_points()
+    pts = tors * 3
+    sc = [0, 1, 2, 3, 4, 5, 6, 7, (1 << 256) - 1, M.R - 1, 8, 9]
+    out = torch.empty((len(pts), 16), dtype=torch.int32, device="cuda")
+    s_t, p_t = _dev_words(sc), _dev_points(pts)
+    ctx.ec_mul(s_t.data_ptr(), p_t.data_ptr(), len(pts), out.data_ptr())
+    torch.cuda.synchronize()
+    got = _host_points(out)
+    for i in range(len(pts)):
+        assert got[i] == M.mul(sc[i], pts[i]), i
