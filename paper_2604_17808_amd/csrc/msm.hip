@@ -27,6 +27,7 @@
 #include "host_field.hpp"
 
 #include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/iterator/counting_iterator.hpp>
 
 namespace frntt {
 namespace {
@@ -201,13 +202,20 @@ __device__ FRNTT_INLINE void load_scalar(const u32x4* p, uint32_t* s) {
 
 // ---- Bucketize ------------------------------------------------------------
 //
-// The argsort of every window's digits is one radix sort of the pairs
-// (k 2^c + digit, point index) over all windows (rocPRIM's device radix
-// sort); window k's entries then fill positions [k n, (k + 1) n) in digit
-// order, and the bucket bounds are the runs of equal keys.
+// The argsort of every window's digits is one stable radix sort of all
+// windows' entries (rocPRIM's device radix sort), with each entry's
+// position k n + i as its value. For c <= 16 the key is the digit alone
+// (two 8-bit passes): the input is window-major and the sort is stable, so
+// the entries of bucket (k, digit) still form one run (runs of equal digits,
+// split by window). For wider windows the key is k 2^c + digit, which takes
+// no more passes than the digit alone, and the values are read from an
+// array rather than a counting iterator (measured faster at those sizes).
+// The runs are the bucket lists.
+constexpr int kDigitOnlyMaxWindow = 16;
 
-// Points into their prepared form (96 bytes per point),
-// and the sort's input pairs: key k 2^c + digit at k n + i, value i.
+// Points into their prepared form (96 bytes per point), and the sort keys:
+// digit k of point i (or k 2^c + digit) at k n + i, with the value k n + i
+// written beside it when vals is not null.
 __global__ __launch_bounds__(kMsmThreads) void msm_prep_kernel(const u32x4* __restrict__ pts,
                                                                const u32x4* __restrict__ sc, int64_t n, int c,
                                                                int K, u32x4* __restrict__ prep,
@@ -222,27 +230,37 @@ __global__ __launch_bounds__(kMsmThreads) void msm_prep_kernel(const u32x4* __re
     uint32_t s[8];
     load_scalar(sc + 2 * i, s);
     for (int k = 0; k < K; ++k) {
-      keys[(int64_t)k * n + i] = ((uint32_t)k << c) | window_digit(s, c, k);
-      vals[(int64_t)k * n + i] = (uint32_t)i;
+      keys[(int64_t)k * n + i] = (c > kDigitOnlyMaxWindow ? (uint32_t)k << c : 0u) | window_digit(s, c, k);
+      if (vals) vals[(int64_t)k * n + i] = (uint32_t)((int64_t)k * n + i);
     }
   }
 }
 
-// Run bounds of the sorted keys: first[key] = start of its run, last[key]
-// = end of its run (both zero for keys that do not occur).
-__global__ __launch_bounds__(kMsmThreads) void msm_bounds_kernel(const uint32_t* __restrict__ keys, int64_t total,
+// Bucket (k 2^c + digit) of sorted entry q: its key, or for digit-only keys
+// the digit and the window of its value k n + i.
+__device__ FRNTT_INLINE int64_t bucket_of(const uint32_t* keys, const uint32_t* vals, int64_t q, uint32_t n, int c) {
+  if (c > kDigitOnlyMaxWindow) return keys[q];
+  return ((int64_t)(vals[q] / n) << c) | keys[q];
+}
+
+// Run bounds of the sorted entries: first[g] = start of bucket g's run and
+// last[g] = its end (both zero for buckets without entries).
+__global__ __launch_bounds__(kMsmThreads) void msm_bounds_kernel(const uint32_t* __restrict__ keys,
+                                                                 const uint32_t* __restrict__ vals, int64_t n,
+                                                                 int c, int64_t total,
                                                                  uint32_t* __restrict__ first,
                                                                  uint32_t* __restrict__ last) {
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total;
-       p += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t key = keys[p];
-    if (p == 0 || keys[p - 1] != key) first[key] = (uint32_t)p;
-    if (p == total - 1 || keys[p + 1] != key) last[key] = (uint32_t)(p + 1);
+  const uint32_t n32 = (uint32_t)n;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t g = bucket_of(keys, vals, q, n32, c);
+    if (q == 0 || bucket_of(keys, vals, q - 1, n32, c) != g) first[g] = (uint32_t)q;
+    if (q == total - 1 || bucket_of(keys, vals, q + 1, n32, c) != g) last[g] = (uint32_t)(q + 1);
   }
 }
 
-// Bucket sizes and list starts within each window's list; bucket 0 (digit
-// zero) is left empty, since its points never reach the result.
+// Bucket sizes and list starts; bucket 0 (digit zero) is left empty, since
+// its points never reach the result.
 __global__ __launch_bounds__(kMsmThreads) void msm_counts_kernel(uint32_t* __restrict__ first,
                                                                  const uint32_t* __restrict__ last,
                                                                  uint32_t* __restrict__ counts, int64_t n, int c,
@@ -250,10 +268,9 @@ __global__ __launch_bounds__(kMsmThreads) void msm_counts_kernel(uint32_t* __res
   const int64_t total = (int64_t)K << c;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
        g += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t k = g >> c;
     const uint32_t cnt = (g & ((1 << c) - 1)) ? last[g] - first[g] : 0u;
     counts[g] = cnt;
-    first[g] = cnt ? (uint32_t)(first[g] - k * n) : 0u;
+    if (!cnt) first[g] = 0u;
   }
 }
 
@@ -274,12 +291,12 @@ constexpr int kChunk0 = 32, kChunk = 32;
 // reached through the index list) or a partial sum.
 struct PointItems {
   const u32x4* prep;
-  const uint32_t* idx;    // window k's list at idx + k n
-  const uint32_t* start;  // bucket list starts within the window's list
+  const uint32_t* idx;    // sorted entries: k n + point index
+  const uint32_t* start;  // bucket list starts in the sorted entries
   int64_t n;
 };
 // The same points already gathered into bucket order (the presorted layout
-// of the Presort-PPG baseline): window k's list at pts + 6 k n.
+// of the Presort-PPG baseline), at the positions of the sorted entries.
 struct SortedItems {
   const u32x4* pts;
   const uint32_t* start;
@@ -294,11 +311,12 @@ struct PartialItems {
 // Sum of items [lo, hi) of bucket g (window k), hi > lo
 __device__ FRNTT_INLINE ept sum_items(const PointItems& S, int64_t g, int64_t k, uint32_t lo, uint32_t hi,
                                       const MsmConsts& C) {
-  const uint32_t* list = S.idx + k * S.n + S.start[g];
-  const u32x4* p0 = S.prep + 6 * (int64_t)list[lo];
+  const uint32_t* list = S.idx + S.start[g];
+  const uint32_t off = (uint32_t)(k * S.n);
+  const u32x4* p0 = S.prep + 6 * (int64_t)(list[lo] - off);
   ept acc = from_prepared(load_fr(p0), load_fr(p0 + 2), C);
   for (uint32_t i = lo + 1; i < hi; ++i) {
-    const u32x4* p = S.prep + 6 * (int64_t)list[i];
+    const u32x4* p = S.prep + 6 * (int64_t)(list[i] - off);
     acc = add_mixed(acc, load_fr(p), load_fr(p + 2), load_fr(p + 4), C);
   }
   return acc;
@@ -306,7 +324,7 @@ __device__ FRNTT_INLINE ept sum_items(const PointItems& S, int64_t g, int64_t k,
 
 __device__ FRNTT_INLINE ept sum_items(const SortedItems& S, int64_t g, int64_t k, uint32_t lo, uint32_t hi,
                                       const MsmConsts& C) {
-  const u32x4* list = S.pts + 6 * (k * S.n + S.start[g]);
+  const u32x4* list = S.pts + 6 * (int64_t)S.start[g];
   const u32x4* p0 = list + 6 * (int64_t)lo;
   ept acc = from_prepared(load_fr(p0), load_fr(p0 + 2), C);
   for (uint32_t i = lo + 1; i < hi; ++i) {
@@ -447,11 +465,12 @@ __global__ __launch_bounds__(kMsmThreads) void msm_chunk_kernel(Items S, const u
 // Presort-PPG baseline: every window's points written out in bucket order
 // (96 bytes per (window, point) pair) before the accumulation reads them.
 __global__ __launch_bounds__(kMsmThreads) void msm_gather_kernel(const u32x4* __restrict__ prep,
-                                                                 const uint32_t* __restrict__ idx, int64_t total,
-                                                                 u32x4* __restrict__ sorted) {
+                                                                 const uint32_t* __restrict__ idx, int64_t n,
+                                                                 int64_t total, u32x4* __restrict__ sorted) {
+  const uint32_t n32 = (uint32_t)n;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total;
        p += (int64_t)gridDim.x * blockDim.x) {
-    const u32x4* src = prep + 6 * (int64_t)idx[p];
+    const u32x4* src = prep + 6 * (int64_t)(idx[p] % n32);
 #pragma unroll
     for (int i = 0; i < 6; ++i) sorted[6 * p + i] = src[i];
   }
@@ -857,9 +876,9 @@ struct MsmLayout {
 };
 
 // Workspace: prepared points; counts, run starts and ends, tile sums; the
-// chunk counts and starts of every level; the sorted index lists; the
-// sort's input keys, output keys and input values, and its temporary
-// storage; the partial sums of every level; two (B, W) buffer pairs of
+// chunk counts and starts of every level; the sorted entries; the sort's
+// input and output keys (and input values for wide windows) and its
+// temporary storage; the partial sums of every level; two (B, W) buffer pairs of
 // K 2^c points; for the Presort-PPG baseline, the points in bucket order.
 MsmLayout msm_layout(int64_t n, int c, bool presort) {
   MsmLayout L;
@@ -875,13 +894,19 @@ MsmLayout msm_layout(int64_t n, int c, bool presort) {
   L.cnt = up(nb * 4 * 4);
   L.lvl = up(nb * 4 * 2 * (size_t)L.levels);
   L.idx = up(K * (size_t)n * 4);
-  L.sort = 3 * L.idx;
-  L.key_bits = 0;
-  while (((size_t)1 << L.key_bits) < nb) ++L.key_bits;
+  const bool digit_only = c <= kDigitOnlyMaxWindow;
+  L.sort = (digit_only ? 2 : 3) * L.idx;
+  L.key_bits = (unsigned)c;
+  if (!digit_only)
+    while (((size_t)1 << L.key_bits) < nb) ++L.key_bits;
   size_t tmp = 0;
-  (void)rocprim::radix_sort_pairs(nullptr, tmp, (const uint32_t*)nullptr, (uint32_t*)nullptr,
-                                  (const uint32_t*)nullptr, (uint32_t*)nullptr, K * (size_t)n, 0u,
-                                  L.key_bits);
+  if (digit_only)
+    (void)rocprim::radix_sort_pairs(nullptr, tmp, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                    rocprim::counting_iterator<uint32_t>(0u), (uint32_t*)nullptr, K * (size_t)n, 0u,
+                                    L.key_bits);
+  else
+    (void)rocprim::radix_sort_pairs(nullptr, tmp, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                    (const uint32_t*)nullptr, (uint32_t*)nullptr, K * (size_t)n, 0u, L.key_bits);
   L.sort_tmp = up(tmp);
   L.part = up((size_t)off * 128);
   L.pts = up(nb * 128 * 4);
@@ -1013,9 +1038,10 @@ int msm_run(frntt_ctx* ctx, const void* scalars, const void* points, int64_t n, 
   p += lay.lvl;
   uint32_t* idx = (uint32_t*)p;
   p += lay.idx;
+  const bool digit_only = c <= kDigitOnlyMaxWindow;
   uint32_t* keys_in = (uint32_t*)p;
   uint32_t* keys_out = (uint32_t*)(p + lay.idx);
-  uint32_t* vals_in = (uint32_t*)(p + 2 * lay.idx);
+  uint32_t* vals_in = digit_only ? nullptr : (uint32_t*)(p + 2 * lay.idx);
   p += lay.sort;
   void* sort_tmp = p;
   p += lay.sort_tmp;
@@ -1033,14 +1059,17 @@ int msm_run(frntt_ctx* ctx, const void* scalars, const void* points, int64_t n, 
   msm_prep_kernel<<<grid_of(ctx, n, false), kMsmThreads, 0, st>>>((const u32x4*)points, (const u32x4*)scalars, n,
                                                                    c, K, prep, keys_in, vals_in, C);
   size_t tmp_bytes = lay.sort_tmp;
-  const hipError_t se = rocprim::radix_sort_pairs(sort_tmp, tmp_bytes, (const uint32_t*)keys_in, keys_out,
-                                                  (const uint32_t*)vals_in, idx, (size_t)total, 0u, lay.key_bits,
-                                                  st);
+  const hipError_t se =
+      digit_only ? rocprim::radix_sort_pairs(sort_tmp, tmp_bytes, (const uint32_t*)keys_in, keys_out,
+                                             rocprim::counting_iterator<uint32_t>(0u), idx, (size_t)total, 0u,
+                                             lay.key_bits, st)
+                 : rocprim::radix_sort_pairs(sort_tmp, tmp_bytes, (const uint32_t*)keys_in, keys_out,
+                                             (const uint32_t*)vals_in, idx, (size_t)total, 0u, lay.key_bits, st);
   if (se != hipSuccess) return set_hip_error(ctx, se);
-  msm_bounds_kernel<<<grid_of(ctx, total, true), kMsmThreads, 0, st>>>(keys_out, total, start, ends);
+  msm_bounds_kernel<<<grid_of(ctx, total, true), kMsmThreads, 0, st>>>(keys_out, idx, n, c, total, start, ends);
   msm_counts_kernel<<<grid_of(ctx, nb, false), kMsmThreads, 0, st>>>(start, ends, counts, n, c, K);
   if (presort) {
-    msm_gather_kernel<<<grid_of(ctx, total, false), kMsmThreads, 0, st>>>(prep, idx, total, sorted);
+    msm_gather_kernel<<<grid_of(ctx, total, false), kMsmThreads, 0, st>>>(prep, idx, n, total, sorted);
     launch_accumulation(ctx, SortedItems{sorted, start, n}, lay, counts, tsum, lvl, part, c, K, B0, st, C);
   } else {
     launch_accumulation(ctx, PointItems{prep, idx, start, n}, lay, counts, tsum, lvl, part, c, K, B0, st, C);
