@@ -33,6 +33,7 @@ namespace frntt {
 namespace {
 
 constexpr int kMsmThreads = 256;
+constexpr int kPrepStride = 8;  // u32x4 per prepared point (96 bytes used of 128)
 constexpr int kScanThreads = 1024;
 constexpr uint32_t kCurveA = 168700, kCurveD = 168696;
 
@@ -213,7 +214,9 @@ __device__ FRNTT_INLINE void load_scalar(const u32x4* p, uint32_t* s) {
 // The runs are the bucket lists.
 constexpr int kDigitOnlyMaxWindow = 16;
 
-// Points into their prepared form (96 bytes per point), and the sort keys:
+// Points into their prepared form (96 bytes in a 128-byte slot per point:
+// a gather of one point then reads one 128-byte line, where 96-byte slots
+// straddle two lines half the time), and the sort keys:
 // digit k of point i (or k 2^c + digit) at k n + i, with the value k n + i
 // written beside it when vals is not null.
 __global__ __launch_bounds__(kMsmThreads) void msm_prep_kernel(const u32x4* __restrict__ pts,
@@ -224,9 +227,9 @@ __global__ __launch_bounds__(kMsmThreads) void msm_prep_kernel(const u32x4* __re
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     fr_t ymx, ypx, kt;
     prepare_point(pts + 4 * i, &ymx, &ypx, &kt, C);
-    store_fr(prep + 6 * i, ymx);
-    store_fr(prep + 6 * i + 2, ypx);
-    store_fr(prep + 6 * i + 4, kt);
+    store_fr(prep + kPrepStride * i, ymx);
+    store_fr(prep + kPrepStride * i + 2, ypx);
+    store_fr(prep + kPrepStride * i + 4, kt);
     uint32_t s[8];
     load_scalar(sc + 2 * i, s);
     for (int k = 0; k < K; ++k) {
@@ -313,10 +316,10 @@ __device__ FRNTT_INLINE ept sum_items(const PointItems& S, int64_t g, int64_t k,
                                       const MsmConsts& C) {
   const uint32_t* list = S.idx + S.start[g];
   const uint32_t off = (uint32_t)(k * S.n);
-  const u32x4* p0 = S.prep + 6 * (int64_t)(list[lo] - off);
+  const u32x4* p0 = S.prep + kPrepStride * (int64_t)(list[lo] - off);
   ept acc = from_prepared(load_fr(p0), load_fr(p0 + 2), C);
   for (uint32_t i = lo + 1; i < hi; ++i) {
-    const u32x4* p = S.prep + 6 * (int64_t)(list[i] - off);
+    const u32x4* p = S.prep + kPrepStride * (int64_t)(list[i] - off);
     acc = add_mixed(acc, load_fr(p), load_fr(p + 2), load_fr(p + 4), C);
   }
   return acc;
@@ -470,7 +473,7 @@ __global__ __launch_bounds__(kMsmThreads) void msm_gather_kernel(const u32x4* __
   const uint32_t n32 = (uint32_t)n;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total;
        p += (int64_t)gridDim.x * blockDim.x) {
-    const u32x4* src = prep + 6 * (int64_t)(idx[p] % n32);
+    const u32x4* src = prep + kPrepStride * (int64_t)(idx[p] % n32);
 #pragma unroll
     for (int i = 0; i < 6; ++i) sorted[6 * p + i] = src[i];
   }
@@ -890,7 +893,7 @@ MsmLayout msm_layout(int64_t n, int c, bool presort) {
     off += (int64_t)K * L.cw[i];
   }
   const auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
-  L.prep = up((size_t)n * 96);
+  L.prep = up((size_t)n * 16 * kPrepStride);
   L.cnt = up(nb * 4 * 4);
   L.lvl = up(nb * 4 * 2 * (size_t)L.levels);
   L.idx = up(K * (size_t)n * 4);
