@@ -13,12 +13,13 @@
 // Coordinates are kept in Montgomery form (R = 2^261) and multiplied with the
 // library's 29-bit-limb Montgomery product.
 //
-// Bucketize is a counting sort per window (histogram, exclusive scan, then
-// scatter of point indices), which is the argsort of the paper's step; the
-// order of indices inside a bucket is left free, since a bucket's sum does
-// not depend on it. The paper's "layout stationary" point is kept: the
-// sorted index lists are gathered once, and every bucket, window and tree
-// level is a separate data-parallel axis of a launch.
+// Bucketize is one stable radix sort of every window's digits (the argsort
+// of the paper's step); the order of points inside a bucket is free, since
+// a bucket's sum does not depend on it. The dataflow is the paper's layout-
+// stationary one: the accumulation reads each point through the sorted
+// entries, and no presorted copy of the points is written to HBM (the
+// Presort-PPG baseline, which writes one, is kept beside it for comparison).
+// Every bucket, window and tree level is a data-parallel axis of a launch.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -34,7 +35,6 @@ namespace {
 
 constexpr int kMsmThreads = 256;
 constexpr int kPrepStride = 8;  // u32x4 per prepared point (96 bytes used of 128)
-constexpr int kScanThreads = 1024;
 constexpr uint32_t kCurveA = 168700, kCurveD = 168696;
 
 struct MsmConsts {
@@ -266,8 +266,7 @@ __global__ __launch_bounds__(kMsmThreads) void msm_bounds_kernel(const uint32_t*
 // its points never reach the result.
 __global__ __launch_bounds__(kMsmThreads) void msm_counts_kernel(uint32_t* __restrict__ first,
                                                                  const uint32_t* __restrict__ last,
-                                                                 uint32_t* __restrict__ counts, int64_t n, int c,
-                                                                 int K) {
+                                                                 uint32_t* __restrict__ counts, int c, int K) {
   const int64_t total = (int64_t)K << c;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
        g += (int64_t)gridDim.x * blockDim.x) {
@@ -303,7 +302,6 @@ struct PointItems {
 struct SortedItems {
   const u32x4* pts;
   const uint32_t* start;
-  int64_t n;
 };
 struct PartialItems {
   const u32x4* part;      // window k's partials at part + 8 k CW
@@ -1070,10 +1068,10 @@ int msm_run(frntt_ctx* ctx, const void* scalars, const void* points, int64_t n, 
                                              (const uint32_t*)vals_in, idx, (size_t)total, 0u, lay.key_bits, st);
   if (se != hipSuccess) return set_hip_error(ctx, se);
   msm_bounds_kernel<<<grid_of(ctx, total, true), kMsmThreads, 0, st>>>(keys_out, idx, n, c, total, start, ends);
-  msm_counts_kernel<<<grid_of(ctx, nb, false), kMsmThreads, 0, st>>>(start, ends, counts, n, c, K);
+  msm_counts_kernel<<<grid_of(ctx, nb, false), kMsmThreads, 0, st>>>(start, ends, counts, c, K);
   if (presort) {
     msm_gather_kernel<<<grid_of(ctx, total, false), kMsmThreads, 0, st>>>(prep, idx, n, total, sorted);
-    launch_accumulation(ctx, SortedItems{sorted, start, n}, lay, counts, tsum, lvl, part, c, K, B0, st, C);
+    launch_accumulation(ctx, SortedItems{sorted, start}, lay, counts, tsum, lvl, part, c, K, B0, st, C);
   } else {
     launch_accumulation(ctx, PointItems{prep, idx, start, n}, lay, counts, tsum, lvl, part, c, K, B0, st, C);
   }
