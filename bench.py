@@ -354,7 +354,8 @@ def bench_f4(ctx, torch, fr, stream, steps):
     MSM runs 2^22 to 2^26): milliseconds per MSM, points per second, the rate of
     Montgomery-product multiply-adds the whole MSM sustains, and the time of
     the Presort-PPG baseline (the paper's dataflow baseline) beside it up to
-    2^24. Points are k_i G
+    2^24, and a batch of four MSMs in one call (frntt_msm_batch) against
+    four single calls at 2^20 and 2^22. Points are k_i G
     from the batch scalar multiplication, scalars uniform field elements."""
     out = {}
     for log_n in (20, 22, 24, 26):
@@ -377,6 +378,16 @@ def bench_f4(ctx, torch, fr, stream, steps):
         mads = msm_products(n, c) * MONT_MADS
         row = {"window": c, "ms": round(t * 1e3, 3), "mpoints_s": round(n / t / 1e6, 2),
                "tmad_s": round(mads / t / 1e12, 3)}
+        if log_n <= 22:
+            # four independent MSMs in one batched call (side streams) against
+            # the same four one after another
+            outs = [torch.empty(16, dtype=torch.int32, device="cuda:0") for _ in range(4)]
+            log(f"f4: msm 2^{log_n} batch of 4")
+            tq = time_op(torch, lambda: ctx.msm_batch([sc.data_ptr()] * 4, [pts.data_ptr()] * 4, [n] * 4,
+                                                      [q.data_ptr() for q in outs], 0, stream), steps, 1) * 1e-3
+            row["batch4_ms"] = round(tq * 1e3, 3)
+            row["batch4_speedup"] = round(4 * t / tq, 3)
+            del outs
         if log_n <= 24:  # the baseline's presorted copy is K n 96 bytes (80 GB at 2^26)
             log(f"f4: msm 2^{log_n} Presort-PPG baseline")
             tb = time_op(torch, lambda: ctx.msm_presort(sc.data_ptr(), pts.data_ptr(), n, o.data_ptr(), 0, stream),

@@ -307,6 +307,18 @@ int frntt_rns_field_mont_mul(frntt_rns_field *f, const void *a, const void *b, v
  * window outside [0, 20]), EALIGN, ENOMEM, ESTATE (stream capture), EHIP. */
 int frntt_msm(frntt_ctx *ctx, const void *scalars, const void *points, int64_t n, int window, void *out,
               void *stream);
+/* Several independent MSMs in one call: MSM i reads scalars[i] and
+ * points[i] (n[i] points) and writes out[i], with the layouts, window and
+ * errors of frntt_msm. They run on up to three streams of the context's own
+ * (default priority), and `stream` waits for all of them, so that one MSM's
+ * latency-bound tail (small reduction levels, the one-wave window merge)
+ * overlaps another's accumulation. Every argument is checked before
+ * anything is enqueued; a later failure (e.g. ENOMEM for scratch) leaves
+ * the MSMs before it enqueued. Each side stream holds its own scratch
+ * (frntt_msm_workspace_bytes of the largest MSM it ran). Calls on one
+ * context enqueue one batch at a time. ESTATE under a stream capture. */
+int frntt_msm_batch(frntt_ctx *ctx, const void *const *scalars, const void *const *points, const int64_t *n,
+                    int count, int window, void *const *out, void *stream);
 /* The same MSM by the paper's dataflow baseline, Presort-PPG (Background,
  * "Presorting Pippenger"; Table 2): every window's points are first written
  * to HBM in bucket order (96 bytes per point and window) and the bucket

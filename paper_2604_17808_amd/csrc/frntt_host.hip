@@ -550,6 +550,7 @@ int frntt_ctx_destroy(frntt_ctx* ctx) {
     if (ctx->valid_flag) hipFree(ctx->valid_flag);
     if (ctx->table_mem) hipFree(ctx->table_mem);
     destroy_rns_field(ctx->rns_default);
+    destroy_msm_streams(ctx);
     for (auto& kv : ctx->pass_tw) hipFree(kv.second);
   }
   delete ctx;

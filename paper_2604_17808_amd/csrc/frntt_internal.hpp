@@ -14,6 +14,7 @@
 
 namespace frntt {
 
+struct MsmStreams;
 __global__ void ntt_pass_bfly_kernel(PassParams P, DevTables T);
 
 __global__ void ntt_batch_kernel(BatchParams B);
@@ -90,6 +91,7 @@ struct frntt_ctx {
   unsigned int* valid_flag = nullptr;  // device flag for FRNTT_VALIDATE
   void* noalloc_scratch = nullptr;     // this device's static scratch of ntt_transform_noalloc
   frntt_rns_field* rns_default = nullptr;  // RNS lazy product over Fr (BN254), built at creation
+  frntt::MsmStreams* msm_streams = nullptr;  // side streams of frntt_msm_batch, made on first use
   // plan overrides [algo][log_n]
   frntt::Plan plan_override[3][29];
   bool has_override[3][29] = {};
@@ -112,6 +114,9 @@ int set_hip_error(const frntt_ctx* ctx, hipError_t e);
 int build_rns_tables(frntt_ctx* ctx);
 int create_rns_field(frntt_ctx* ctx, const uint32_t* m, int mw, frntt_rns_field** out);
 void destroy_rns_field(frntt_rns_field* f);
+// Release the side streams and events of frntt_msm_batch (after the device
+// has been synchronised).
+void destroy_msm_streams(frntt_ctx* ctx);
 // Default or overridden plan for (algo, log_n); algo must be BUTTERFLY or MFMA.
 // Takes ctx->mu.
 Plan plan_for(const frntt_ctx* ctx, int algo, int log_n);

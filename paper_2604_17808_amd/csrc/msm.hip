@@ -30,6 +30,8 @@
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/iterator/counting_iterator.hpp>
 
+#include <mutex>
+
 namespace frntt {
 namespace {
 
@@ -1091,9 +1093,96 @@ int msm_run(frntt_ctx* ctx, const void* scalars, const void* points, int64_t n, 
 }
 
 }  // namespace
+
+// Side streams of frntt_msm_batch: independent MSMs run on them so that one
+// MSM's latency-bound tail (small reduction levels, the one-wave merge)
+// overlaps another's accumulation. Default stream priority throughout.
+constexpr int kMsmSideStreams = 3;
+
+struct MsmStreams {
+  hipStream_t s[kMsmSideStreams] = {};
+  hipEvent_t start = nullptr;  // recorded on the caller's stream
+  hipEvent_t done[kMsmSideStreams] = {};
+  std::mutex mu;               // one batch's enqueue sequence at a time
+};
+
+void destroy_msm_streams(frntt_ctx* ctx) {
+  MsmStreams* m = ctx->msm_streams;
+  if (!m) return;
+  for (int i = 0; i < kMsmSideStreams; ++i) {
+    if (m->s[i]) (void)hipStreamDestroy(m->s[i]);
+    if (m->done[i]) (void)hipEventDestroy(m->done[i]);
+  }
+  if (m->start) (void)hipEventDestroy(m->start);
+  delete m;
+  ctx->msm_streams = nullptr;
+}
+
+namespace {
+
+int get_msm_streams(frntt_ctx* ctx, MsmStreams** out) {
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (!ctx->msm_streams) {
+    MsmStreams* m = new MsmStreams();
+    hipError_t e = hipEventCreateWithFlags(&m->start, hipEventDisableTiming);
+    for (int i = 0; i < kMsmSideStreams && e == hipSuccess; ++i) {
+      e = hipStreamCreateWithFlags(&m->s[i], hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&m->done[i], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+      ctx->msm_streams = m;
+      destroy_msm_streams(ctx);
+      return set_hip_error(ctx, e);
+    }
+    ctx->msm_streams = m;
+  }
+  *out = ctx->msm_streams;
+  return FRNTT_OK;
+}
+
+int msm_args_ok(const void* scalars, const void* points, int64_t n, const void* out) {
+  if (!out || n < 0 || (n > 0 && (!scalars || !points))) return FRNTT_EINVAL;
+  if (n > kMsmMaxPoints) return FRNTT_ERANGE;
+  if ((((uintptr_t)scalars | (uintptr_t)points) & 15) != 0) return FRNTT_EALIGN;
+  return FRNTT_OK;
+}
+
+}  // namespace
 }  // namespace frntt
 
 extern "C" {
+
+int frntt_msm_batch(frntt_ctx* ctx, const void* const* scalars, const void* const* points, const int64_t* n,
+                    int count, int window, void* const* out, void* stream) {
+  if (!ctx || count < 0 || (count > 0 && (!scalars || !points || !n || !out))) return FRNTT_EINVAL;
+  if (window < 0 || window > kMsmMaxWindow) return FRNTT_ERANGE;
+  for (int i = 0; i < count; ++i) {
+    const int rc = msm_args_ok(scalars[i], points[i], n[i], out[i]);
+    if (rc != FRNTT_OK) return rc;
+  }
+  if (count == 0) return FRNTT_OK;
+  const hipStream_t st = (hipStream_t)stream;
+  if (stream_capturing(st)) return FRNTT_ESTATE;
+  MsmDeviceGuard guard(ctx->device);
+  MsmStreams* ms = nullptr;
+  int rc = get_msm_streams(ctx, &ms);
+  if (rc != FRNTT_OK) return rc;
+  std::lock_guard<std::mutex> lk(ms->mu);
+  const int used = count < kMsmSideStreams ? count : kMsmSideStreams;
+  hipError_t e = hipEventRecord(ms->start, st);
+  for (int j = 0; j < used && e == hipSuccess; ++j) e = hipStreamWaitEvent(ms->s[j], ms->start, 0);
+  if (e != hipSuccess) return set_hip_error(ctx, e);
+  for (int i = 0; i < count && rc == FRNTT_OK; ++i)
+    rc = msm_run(ctx, scalars[i], points[i], n[i], window, out[i], ms->s[i % used], false);
+  // the caller's stream waits for everything that was enqueued, also after
+  // an error
+  for (int j = 0; j < used; ++j) {
+    e = hipEventRecord(ms->done[j], ms->s[j]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, ms->done[j], 0);
+    if (e != hipSuccess && rc == FRNTT_OK) rc = set_hip_error(ctx, e);
+  }
+  return rc;
+}
 
 int frntt_msm(frntt_ctx* ctx, const void* scalars, const void* points, int64_t n, int window, void* out,
               void* stream) {

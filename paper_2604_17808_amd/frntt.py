@@ -87,6 +87,8 @@ SIGNATURES = {
     "frntt_rns_field_mont_mul": (_i, [_vp, _vp, _vp, _vp, ctypes.c_int64, _vp]),
     "frntt_msm": (_i, [_vp, _vp, _vp, ctypes.c_int64, _i, _vp, _vp]),
     "frntt_msm_presort": (_i, [_vp, _vp, _vp, ctypes.c_int64, _i, _vp, _vp]),
+    "frntt_msm_batch": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_int64), _i,
+                             _i, ctypes.POINTER(_vp), _vp]),
     "frntt_msm_window": (_i, [ctypes.c_int64]),
     "frntt_ec_mul": (_i, [_vp, _vp, _vp, ctypes.c_int64, _vp, _vp]),
     "frntt_msm_workspace_bytes": (_sz, [ctypes.c_int64, _i]),
@@ -280,6 +282,15 @@ class Context:
     # scalars n x 8 words, points n x 16 words (x, y), out 16 words (x, y)
     def msm(self, scalars: int, points: int, n: int, out: int, window: int = 0, stream: int = 0):
         return _check(lib().frntt_msm(self._h, scalars, points, n, window, out, stream), "frntt_msm")
+
+    def msm_batch(self, scalars, points, ns, outs, window: int = 0, stream: int = 0):
+        """Independent MSMs (lists of device pointers and sizes) in one call."""
+        k = len(ns)
+        if not (len(scalars) == len(points) == len(outs) == k):
+            raise ValueError("msm_batch: lists of different lengths")
+        arr = lambda v: (_vp * max(k, 1))(*v)
+        return _check(lib().frntt_msm_batch(self._h, arr(scalars), arr(points), (ctypes.c_int64 * max(k, 1))(*ns),
+                                            k, window, arr(outs), stream), "frntt_msm_batch")
 
     def msm_presort(self, scalars: int, points: int, n: int, out: int, window: int = 0, stream: int = 0):
         """The Presort-PPG baseline of the same MSM (bit-identical)."""

@@ -321,3 +321,41 @@ def test_ec_mul_small_order_points(ctx):
     got = _host_points(out)
     for i in range(len(pts)):
         assert got[i] == M.mul(sc[i], pts[i]), i
+
+
+def test_msm_batch_matches_single_calls(ctx):
+    # independent MSMs of different sizes (one empty) on the side streams,
+    # each against the oracle
+    sizes = [4096 + 3, 0, 17, 40000]
+    cases = []
+    for j, n in enumerate(sizes):
+        pts, bases, h = _walk_points(n, 1300 + j) if n else ([], [], None)
+        sc = _scalars(n, 1400 + j)
+        want = _walk_expected(sc, bases, h) if n else M.ZERO
+        s_t = _dev_words(sc) if n else torch.zeros((1, 8), dtype=torch.int32, device="cuda")
+        p_t = _dev_points(pts) if n else torch.zeros((1, 16), dtype=torch.int32, device="cuda")
+        cases.append((n, s_t, p_t, torch.full((16,), 5, dtype=torch.int32, device="cuda"), want))
+    for window in (0, 9):
+        ctx.msm_batch([c[1].data_ptr() for c in cases], [c[2].data_ptr() for c in cases],
+                      [c[0] for c in cases], [c[3].data_ptr() for c in cases], window)
+        torch.cuda.synchronize()
+        for n, _, _, o, want in cases:
+            assert _host_point(o) == want, (n, window)
+
+
+def test_msm_batch_argument_errors(ctx):
+    t = torch.zeros((8, 16), dtype=torch.int32, device="cuda")
+    o = torch.full((16,), 3, dtype=torch.int32, device="cuda")
+    p = t.data_ptr()
+    with pytest.raises(B.FrnttError) as e:
+        ctx.msm_batch([p, p], [p, p + 4], [1, 1], [o.data_ptr(), o.data_ptr()])
+    assert e.value.status == B.EALIGN
+    with pytest.raises(B.FrnttError) as e:
+        ctx.msm_batch([p], [p], [-1], [o.data_ptr()])
+    assert e.value.status == B.EINVAL
+    with pytest.raises(B.FrnttError) as e:
+        ctx.msm_batch([p], [p], [1], [o.data_ptr()], window=21)
+    assert e.value.status == B.ERANGE
+    torch.cuda.synchronize()
+    assert bool((o == 3).all())  # nothing ran
+    assert ctx.msm_batch([], [], [], []) == B.OK
