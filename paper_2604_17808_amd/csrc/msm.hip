@@ -531,21 +531,31 @@ __global__ __launch_bounds__(kMsmThreads) void msm_bucket_final_kernel(ChunkLeve
 // W_b <- W_2b + W_(2b+1) + B_(2b+1) and B_b <- 2 (B_2b + B_(2b+1)).
 // Entries of window k sit at k 2^c + index in every buffer. On the first
 // level every W is zero; on the last one (s = 0) the new B is not needed.
+// The two updates are independent chains of about 17 products each, so
+// they run on alternate whole waves (even waves W, odd waves B): the small
+// levels, where a level's time is one thread's chain, take half as long,
+// and no wave diverges. Launched with two threads per pair.
 __global__ __launch_bounds__(kMsmThreads) void msm_reduce_kernel(const u32x4* __restrict__ Bin,
                                                                  const u32x4* __restrict__ Win,
                                                                  u32x4* __restrict__ Bout,
                                                                  u32x4* __restrict__ Wout, int c, int K, int s,
                                                                  int first, MsmConsts C) {
   const int64_t total = (int64_t)K << s;
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
-       g += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t pair_waves = ((int64_t)gridDim.x * blockDim.x) >> 7;  // blockDim is a multiple of 128
+  const bool form_b = (wave & 1) != 0;
+  if (form_b && s == 0) return;
+  for (int64_t g = (wave >> 1) * 64 + (threadIdx.x & 63); g < total; g += pair_waves * 64) {
     const int64_t k = g >> s, b = g & ((1 << s) - 1);
     const int64_t l = (k << c) + 2 * b, o = (k << c) + b;
     const ept BR = load_ept(Bin + 8 * (l + 1));
-    ept w = BR;
-    if (!first) w = add_full(add_full(load_ept(Win + 8 * l), load_ept(Win + 8 * (l + 1)), C), BR, C);
-    store_ept(Wout + 8 * o, w);
-    if (s > 0) store_ept(Bout + 8 * o, dbl(add_full(load_ept(Bin + 8 * l), BR, C), C));
+    if (form_b) {
+      store_ept(Bout + 8 * o, dbl(add_full(load_ept(Bin + 8 * l), BR, C), C));
+    } else {
+      ept w = BR;
+      if (!first) w = add_full(add_full(load_ept(Win + 8 * l), load_ept(Win + 8 * (l + 1)), C), BR, C);
+      store_ept(Wout + 8 * o, w);
+    }
   }
 }
 
@@ -1094,7 +1104,7 @@ int msm_run(frntt_ctx* ctx, const void* scalars, const void* points, int64_t n, 
   }
   u32x4 *bi = B0, *wi = W0, *bo = B1, *wo = W1;
   for (int s = c - 1; s >= 0; --s) {
-    msm_reduce_kernel<<<grid_of(ctx, (int64_t)K << s, false), kMsmThreads, 0, st>>>(bi, wi, bo, wo, c, K, s,
+    msm_reduce_kernel<<<grid_of(ctx, (int64_t)K << (s + 1), false), kMsmThreads, 0, st>>>(bi, wi, bo, wo, c, K, s,
                                                                                    s == c - 1, C);
     u32x4* t = bi;
     bi = bo;
