@@ -241,26 +241,77 @@ __global__ __launch_bounds__(kMsmThreads) void msm_prep_kernel(const u32x4* __re
   }
 }
 
-// Bucket (k 2^c + digit) of sorted entry q: its key, or for digit-only keys
+// Run bounds of the sorted entries: first[g] = start of bucket g's run and
+// last[g] = its end (both zero for buckets without entries). Each thread
+// takes four consecutive entries per step: one aligned 16-byte load per
+// array (the workspace arrays start on 256-byte boundaries) plus the two
+// neighbours, so a wave's loads cover whole lines and several are in
+// flight per thread.
+constexpr int kBoundsPerThread = 4;
+
+// Bucket (k 2^c + digit) of a sorted entry: its key, or for digit-only keys
 // the digit and the window of its value k n + i.
-__device__ FRNTT_INLINE int64_t bucket_of(const uint32_t* keys, const uint32_t* vals, int64_t q, uint32_t n, int c) {
-  if (c > kDigitOnlyMaxWindow) return keys[q];
-  return ((int64_t)(vals[q] / n) << c) | keys[q];
+__device__ FRNTT_INLINE int64_t bucket_from(uint32_t key, uint32_t val, uint32_t n, int c) {
+  if (c > kDigitOnlyMaxWindow) return key;
+  return ((int64_t)(val / n) << c) | key;
 }
 
-// Run bounds of the sorted entries: first[g] = start of bucket g's run and
-// last[g] = its end (both zero for buckets without entries).
 __global__ __launch_bounds__(kMsmThreads) void msm_bounds_kernel(const uint32_t* __restrict__ keys,
                                                                  const uint32_t* __restrict__ vals, int64_t n,
                                                                  int c, int64_t total,
                                                                  uint32_t* __restrict__ first,
                                                                  uint32_t* __restrict__ last) {
   const uint32_t n32 = (uint32_t)n;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
-       q += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t g = bucket_of(keys, vals, q, n32, c);
-    if (q == 0 || bucket_of(keys, vals, q - 1, n32, c) != g) first[g] = (uint32_t)q;
-    if (q == total - 1 || bucket_of(keys, vals, q + 1, n32, c) != g) last[g] = (uint32_t)(q + 1);
+  const bool digit_only = c <= kDigitOnlyMaxWindow;
+  const int64_t steps = (total + kBoundsPerThread - 1) / kBoundsPerThread;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < steps;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t q0 = kBoundsPerThread * t;
+    // entries q0 - 1 .. q0 + 4
+    uint32_t kq[kBoundsPerThread + 2] = {}, vq[kBoundsPerThread + 2] = {};
+    if (q0 + kBoundsPerThread <= total) {
+      const u32x4 k4 = *reinterpret_cast<const u32x4*>(keys + q0);
+      kq[1] = k4.x;
+      kq[2] = k4.y;
+      kq[3] = k4.z;
+      kq[4] = k4.w;
+      if (digit_only) {
+        const u32x4 v4 = *reinterpret_cast<const u32x4*>(vals + q0);
+        vq[1] = v4.x;
+        vq[2] = v4.y;
+        vq[3] = v4.z;
+        vq[4] = v4.w;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < kBoundsPerThread; ++j)
+        if (q0 + j < total) {
+          kq[1 + j] = keys[q0 + j];
+          if (digit_only) vq[1 + j] = vals[q0 + j];
+        }
+    }
+    if (q0 > 0) {
+      kq[0] = keys[q0 - 1];
+      if (digit_only) vq[0] = vals[q0 - 1];
+    }
+    if (q0 + kBoundsPerThread < total) {
+      kq[kBoundsPerThread + 1] = keys[q0 + kBoundsPerThread];
+      if (digit_only) vq[kBoundsPerThread + 1] = vals[q0 + kBoundsPerThread];
+    }
+    // their buckets; -1 outside [0, total)
+    int64_t g[kBoundsPerThread + 2];
+#pragma unroll
+    for (int j = 0; j < kBoundsPerThread + 2; ++j) {
+      const int64_t q = q0 - 1 + j;
+      g[j] = (q >= 0 && q < total) ? bucket_from(kq[j], vq[j], n32, c) : -1;
+    }
+#pragma unroll
+    for (int j = 1; j <= kBoundsPerThread; ++j) {
+      const int64_t q = q0 - 1 + j;
+      if (g[j] < 0) break;
+      if (g[j - 1] != g[j]) first[g[j]] = (uint32_t)q;
+      if (g[j + 1] != g[j]) last[g[j]] = (uint32_t)(q + 1);
+    }
   }
 }
 
@@ -1094,7 +1145,8 @@ int msm_run(frntt_ctx* ctx, const void* scalars, const void* points, int64_t n, 
                  : rocprim::radix_sort_pairs(sort_tmp, tmp_bytes, (const uint32_t*)keys_in, keys_out,
                                              (const uint32_t*)vals_in, idx, (size_t)total, 0u, lay.key_bits, st);
   if (se != hipSuccess) return set_hip_error(ctx, se);
-  msm_bounds_kernel<<<grid_of(ctx, total, true), kMsmThreads, 0, st>>>(keys_out, idx, n, c, total, start, ends);
+  const int64_t bound_steps = (total + kBoundsPerThread - 1) / kBoundsPerThread;
+  msm_bounds_kernel<<<grid_of(ctx, bound_steps, true), kMsmThreads, 0, st>>>(keys_out, idx, n, c, total, start, ends);
   msm_counts_kernel<<<grid_of(ctx, nb, false), kMsmThreads, 0, st>>>(start, ends, counts, c, K);
   if (presort) {
     msm_gather_kernel<<<grid_of(ctx, total, false), kMsmThreads, 0, st>>>(prep, idx, n, total, sorted);
