@@ -220,11 +220,13 @@ constexpr int kDigitOnlyMaxWindow = 16;
 // a gather of one point then reads one 128-byte line, where 96-byte slots
 // straddle two lines half the time), and the sort keys:
 // digit k of point i (or k 2^c + digit) at k n + i, with the value k n + i
-// written beside it when vals is not null.
+// written beside it when vals is not null. Digit-only keys (c <= 16) are
+// 16-bit words, which trims the radix sort's traffic.
+template <typename KeyT>
 __global__ __launch_bounds__(kMsmThreads) void msm_prep_kernel(const u32x4* __restrict__ pts,
                                                                const u32x4* __restrict__ sc, int64_t n, int c,
                                                                int K, u32x4* __restrict__ prep,
-                                                               uint32_t* __restrict__ keys,
+                                                               KeyT* __restrict__ keys,
                                                                uint32_t* __restrict__ vals, MsmConsts C) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     fr_t ymx, ypx, kt;
@@ -235,7 +237,7 @@ __global__ __launch_bounds__(kMsmThreads) void msm_prep_kernel(const u32x4* __re
     uint32_t s[8];
     load_scalar(sc + 2 * i, s);
     for (int k = 0; k < K; ++k) {
-      keys[(int64_t)k * n + i] = (c > kDigitOnlyMaxWindow ? (uint32_t)k << c : 0u) | window_digit(s, c, k);
+      keys[(int64_t)k * n + i] = (KeyT)((c > kDigitOnlyMaxWindow ? (uint32_t)k << c : 0u) | window_digit(s, c, k));
       if (vals) vals[(int64_t)k * n + i] = (uint32_t)((int64_t)k * n + i);
     }
   }
@@ -243,8 +245,8 @@ __global__ __launch_bounds__(kMsmThreads) void msm_prep_kernel(const u32x4* __re
 
 // Run bounds of the sorted entries: first[g] = start of bucket g's run and
 // last[g] = its end (both zero for buckets without entries). Each thread
-// takes four consecutive entries per step: one aligned 16-byte load per
-// array (the workspace arrays start on 256-byte boundaries) plus the two
+// takes four consecutive entries per step: one aligned load per array (the
+// workspace arrays start on 256-byte boundaries) plus the two
 // neighbours, so a wave's loads cover whole lines and several are in
 // flight per thread.
 constexpr int kBoundsPerThread = 4;
@@ -256,7 +258,25 @@ __device__ FRNTT_INLINE int64_t bucket_from(uint32_t key, uint32_t val, uint32_t
   return ((int64_t)(val / n) << c) | key;
 }
 
-__global__ __launch_bounds__(kMsmThreads) void msm_bounds_kernel(const uint32_t* __restrict__ keys,
+// four keys from an aligned address
+__device__ FRNTT_INLINE void load_keys4(const uint32_t* p, uint32_t* o) {
+  const u32x4 v = *reinterpret_cast<const u32x4*>(p);
+  o[0] = v.x;
+  o[1] = v.y;
+  o[2] = v.z;
+  o[3] = v.w;
+}
+__device__ FRNTT_INLINE void load_keys4(const uint16_t* p, uint32_t* o) {
+  typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+  const u32x2 v = *reinterpret_cast<const u32x2*>(p);
+  o[0] = v.x & 0xffffu;
+  o[1] = v.x >> 16;
+  o[2] = v.y & 0xffffu;
+  o[3] = v.y >> 16;
+}
+
+template <typename KeyT>
+__global__ __launch_bounds__(kMsmThreads) void msm_bounds_kernel(const KeyT* __restrict__ keys,
                                                                  const uint32_t* __restrict__ vals, int64_t n,
                                                                  int c, int64_t total,
                                                                  uint32_t* __restrict__ first,
@@ -270,11 +290,7 @@ __global__ __launch_bounds__(kMsmThreads) void msm_bounds_kernel(const uint32_t*
     // entries q0 - 1 .. q0 + 4
     uint32_t kq[kBoundsPerThread + 2] = {}, vq[kBoundsPerThread + 2] = {};
     if (q0 + kBoundsPerThread <= total) {
-      const u32x4 k4 = *reinterpret_cast<const u32x4*>(keys + q0);
-      kq[1] = k4.x;
-      kq[2] = k4.y;
-      kq[3] = k4.z;
-      kq[4] = k4.w;
+      load_keys4(keys + q0, kq + 1);
       if (digit_only) {
         const u32x4 v4 = *reinterpret_cast<const u32x4*>(vals + q0);
         vq[1] = v4.x;
@@ -968,7 +984,7 @@ MsmLayout msm_layout(int64_t n, int c, bool presort) {
     while (((size_t)1 << L.key_bits) < nb) ++L.key_bits;
   size_t tmp = 0;
   if (digit_only)
-    (void)rocprim::radix_sort_pairs(nullptr, tmp, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+    (void)rocprim::radix_sort_pairs(nullptr, tmp, (const uint16_t*)nullptr, (uint16_t*)nullptr,
                                     rocprim::counting_iterator<uint32_t>(0u), (uint32_t*)nullptr, K * (size_t)n, 0u,
                                     L.key_bits);
   else
@@ -1118,8 +1134,9 @@ int msm_run(frntt_ctx* ctx, const void* scalars, const void* points, int64_t n, 
   uint32_t* idx = (uint32_t*)p;
   p += lay.idx;
   const bool digit_only = c <= kDigitOnlyMaxWindow;
-  uint32_t* keys_in = (uint32_t*)p;
-  uint32_t* keys_out = (uint32_t*)(p + lay.idx);
+  // 16-bit keys for digit-only sorts, 32-bit otherwise (buffers sized for the latter)
+  void* keys_in = p;
+  void* keys_out = p + lay.idx;
   uint32_t* vals_in = digit_only ? nullptr : (uint32_t*)(p + 2 * lay.idx);
   p += lay.sort;
   void* sort_tmp = p;
@@ -1135,18 +1152,27 @@ int msm_run(frntt_ctx* ctx, const void* scalars, const void* points, int64_t n, 
 
   const int64_t total = (int64_t)K * n;
   zero_words_kernel<<<(unsigned)((2 * nb + 255) / 256), 256, 0, st>>>(start, 2 * nb);
-  msm_prep_kernel<<<grid_of(ctx, n, false), kMsmThreads, 0, st>>>((const u32x4*)points, (const u32x4*)scalars, n,
-                                                                   c, K, prep, keys_in, vals_in, C);
   size_t tmp_bytes = lay.sort_tmp;
-  const hipError_t se =
-      digit_only ? rocprim::radix_sort_pairs(sort_tmp, tmp_bytes, (const uint32_t*)keys_in, keys_out,
-                                             rocprim::counting_iterator<uint32_t>(0u), idx, (size_t)total, 0u,
-                                             lay.key_bits, st)
-                 : rocprim::radix_sort_pairs(sort_tmp, tmp_bytes, (const uint32_t*)keys_in, keys_out,
-                                             (const uint32_t*)vals_in, idx, (size_t)total, 0u, lay.key_bits, st);
-  if (se != hipSuccess) return set_hip_error(ctx, se);
   const int64_t bound_steps = (total + kBoundsPerThread - 1) / kBoundsPerThread;
-  msm_bounds_kernel<<<grid_of(ctx, bound_steps, true), kMsmThreads, 0, st>>>(keys_out, idx, n, c, total, start, ends);
+  if (digit_only) {
+    msm_prep_kernel<uint16_t><<<grid_of(ctx, n, false), kMsmThreads, 0, st>>>(
+        (const u32x4*)points, (const u32x4*)scalars, n, c, K, prep, (uint16_t*)keys_in, nullptr, C);
+    const hipError_t se = rocprim::radix_sort_pairs(sort_tmp, tmp_bytes, (const uint16_t*)keys_in,
+                                                    (uint16_t*)keys_out, rocprim::counting_iterator<uint32_t>(0u),
+                                                    idx, (size_t)total, 0u, lay.key_bits, st);
+    if (se != hipSuccess) return set_hip_error(ctx, se);
+    msm_bounds_kernel<uint16_t><<<grid_of(ctx, bound_steps, true), kMsmThreads, 0, st>>>(
+        (const uint16_t*)keys_out, idx, n, c, total, start, ends);
+  } else {
+    msm_prep_kernel<uint32_t><<<grid_of(ctx, n, false), kMsmThreads, 0, st>>>(
+        (const u32x4*)points, (const u32x4*)scalars, n, c, K, prep, (uint32_t*)keys_in, vals_in, C);
+    const hipError_t se = rocprim::radix_sort_pairs(sort_tmp, tmp_bytes, (const uint32_t*)keys_in,
+                                                    (uint32_t*)keys_out, (const uint32_t*)vals_in, idx,
+                                                    (size_t)total, 0u, lay.key_bits, st);
+    if (se != hipSuccess) return set_hip_error(ctx, se);
+    msm_bounds_kernel<uint32_t><<<grid_of(ctx, bound_steps, true), kMsmThreads, 0, st>>>(
+        (const uint32_t*)keys_out, idx, n, c, total, start, ends);
+  }
   msm_counts_kernel<<<grid_of(ctx, nb, false), kMsmThreads, 0, st>>>(start, ends, counts, c, K);
   if (presort) {
     msm_gather_kernel<<<grid_of(ctx, total, false), kMsmThreads, 0, st>>>(prep, idx, n, total, sorted);
