@@ -335,13 +335,13 @@ MONT_MADS = 162   # 32x32+64-bit multiply-adds of one 9-limb Montgomery product
 
 def msm_products(n, c):
     """Montgomery products of one MSM of n points with c-bit windows, in the
-    a = -1 model the kernels use: the point preparation (5 per point), the
+    a = -1 model the kernels use: the point preparation (4 per point), the
     bucket accumulation (7 per added point), the tree reduction (two
     additions into W, one addition and one doubling into B per bucket pair
     and level: 9 + 9 + 9 + 8), and the window merging (c doublings and one
     addition per window)."""
     K = -(-256 // c)
-    prep = 5 * n
+    prep = 4 * n
     accum = 7 * n * K
     reduce_ = K * ((1 << c) - 1) * (9 + 9 + 9 + 8)
     merge = K * (8 * c + 9 + 1) + 6

@@ -45,6 +45,8 @@ struct MsmConsts {
   fr_t s;     // s = sqrt(-a), Montgomery form
   fr_t sinv;  // s^-1, Montgomery form
   fr_t k;     // 2 d' = -2 d / a, Montgomery form
+  fr_t r2s;   // s 2^522 mod r: x -> x s in Montgomery form, one product
+  fr_t r3sk;  // 2 d' s 2^783 mod r: (x y 2^-261) -> 2 d' s x y in Montgomery form
 };
 
 // extended coordinates, Montgomery form
@@ -171,11 +173,12 @@ __device__ FRNTT_INLINE ept from_prepared(const fr_t& ymx, const fr_t& ypx, cons
 // Prepared form of an affine input point (x, y): y - x', y + x', 2 d' x' y
 // in Montgomery form (x' = s x).
 __device__ FRNTT_INLINE void prepare_point(const u32x4* in, fr_t* ymx, fr_t* ypx, fr_t* kt, const MsmConsts& C) {
-  const fr_t xp = mont_mul(mont_mul(load_fr(in), C.r2), C.s);
-  const fr_t ym = mont_mul(load_fr(in + 2), C.r2);
+  const fr_t x = load_fr(in), y = load_fr(in + 2);
+  const fr_t xp = mont_mul(x, C.r2s);
+  const fr_t ym = mont_mul(y, C.r2);
   *ymx = fr_sub(ym, xp);
   *ypx = fr_add(ym, xp);
-  *kt = mont_mul(mont_mul(xp, ym), C.k);
+  *kt = mont_mul(mont_mul(x, y), C.r3sk);
 }
 
 // Affine (x, y) = (X / (s Z), Y / Z) in canonical form
@@ -912,6 +915,8 @@ MsmConsts make_consts() {
   fe_words(times_pow2(s, 261), &C.s);
   fe_words(times_pow2(sinv, 261), &C.sinv);
   fe_words(times_pow2(k, 261), &C.k);
+  fe_words(times_pow2(s, 522), &C.r2s);
+  fe_words(times_pow2(F.mul(k, s), 783), &C.r3sk);
   return C;
 }
 
